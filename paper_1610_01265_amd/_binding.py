@@ -1,0 +1,242 @@
+"""ctypes binding of libsts.so (include/sts.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.  PyTorch
+supplies device memory and the current HIP stream."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsts.so")
+
+STS_OK, STS_NOT_CONVERGED = 0, 1
+STS_EINVAL, STS_EHIP, STS_ENOMEM, STS_BREAKDOWN = -1, -2, -3, -4
+SPHERICAL, CARTESIAN = 0, 1
+BC_ZEROFLUX, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
+PC_JACOBI, PC_BLOCK_ILU0 = 0, 1
+SHELL_BC = (BC_DIRICHLET, BC_ZEROFLUX, BC_ZEROFLUX, BC_ZEROFLUX, BC_PERIODIC, BC_PERIODIC)
+
+_STATUS = {0: "STS_OK", 1: "STS_NOT_CONVERGED", -1: "STS_EINVAL", -2: "STS_EHIP",
+           -3: "STS_ENOMEM", -4: "STS_BREAKDOWN"}
+
+_lib = None
+
+
+class StsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libsts.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1610_01265_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, D, I = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+    PI, PD = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "sts_create": (I, [ctypes.POINTER(P), I, I, I, I, PD, PD, PD, PI, P]),
+        "sts_destroy": (I, [P]),
+        "sts_set_stream": (I, [P, P]),
+        "sts_last_error": (ctypes.c_char_p, [P]),
+        "sts_num_cells": (ctypes.c_longlong, [P]),
+        "sts_set_spitzer": (I, [P, P, D, P, P, P]),
+        "sts_set_isotropic": (I, [P, D]),
+        "sts_set_dirichlet": (I, [P, I, P, D]),
+        "sts_dt_euler": (I, [P, PD]),
+        "apply_F": (I, [P, P, P, I]),
+        "rkl2_step": (I, [P, P, I, D, I, PI]),
+        "be_pcg_solve": (I, [P, P, P, D, I, PI, D, I, PI, PD]),
+        "sts_be_residual": (I, [P, P, P, D, PD]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["sts_create", "sts_destroy", "sts_set_stream", "sts_last_error", "sts_num_cells",
+            "sts_set_spitzer", "sts_set_isotropic", "sts_set_dirichlet", "sts_dt_euler",
+            "apply_F", "rkl2_step", "be_pcg_solve", "sts_be_residual"]
+
+
+def _ptr(t: torch.Tensor | None, ncell: int, name: str, ncomp: int | None = 1,
+         dtype=torch.float64):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ncomp is not None and t.numel() != ncell * ncomp:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {ncell * ncomp}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _d(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Context:
+    """One grid + one operator (sts_ctx)."""
+
+    def __init__(self, coord, f0, f1, f2, bc=SHELL_BC):
+        lib = load()
+        self._lib = lib
+        a0, p0 = _d(f0)
+        a1, p1 = _d(f1)
+        a2, p2 = _d(f2)
+        self.shape = (len(a0) - 1, len(a1) - 1, len(a2) - 1)
+        self.ncell = self.shape[0] * self.shape[1] * self.shape[2]
+        bcs = (ctypes.c_int * 6)(*bc)
+        h = ctypes.c_void_p()
+        st = lib.sts_create(ctypes.byref(h), int(coord), *self.shape, p0, p1, p2, bcs, _stream())
+        if st != STS_OK:
+            raise StsError(st, "sts_create failed (see stderr)")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sts_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, ok=(STS_OK,)):
+        if st not in ok:
+            raise StsError(st, self._lib.sts_last_error(self._h).decode())
+        return st
+
+    def _sync_stream(self):
+        self._lib.sts_set_stream(self._h, _stream())
+
+    def set_spitzer(self, T, kappa0, b0, b1, b2):
+        self._sync_stream()
+        n = self.ncell
+        self._check(self._lib.sts_set_spitzer(self._h, _ptr(T, n, "T"), float(kappa0),
+                                              _ptr(b0, n, "b0"), _ptr(b1, n, "b1"),
+                                              _ptr(b2, n, "b2")))
+
+    def set_isotropic(self, nu):
+        self._sync_stream()
+        self._check(self._lib.sts_set_isotropic(self._h, float(nu)))
+
+    def set_dirichlet(self, side, values=None, value=0.0):
+        self._sync_stream()
+        nb = self.shape[1] * self.shape[2]
+        self._check(self._lib.sts_set_dirichlet(self._h, int(side), _ptr(values, nb, "values"),
+                                                float(value)))
+
+    def dt_euler(self) -> float:
+        self._sync_stream()
+        out = ctypes.c_double()
+        self._check(self._lib.sts_dt_euler(self._h, ctypes.byref(out)))
+        return out.value
+
+    def _ncomp(self, u):
+        nc = u.numel() // self.ncell
+        if nc * self.ncell != u.numel():
+            raise ValueError("field size is not a multiple of the cell count")
+        return nc
+
+    def apply_F(self, u, out=None):
+        self._sync_stream()
+        nc = self._ncomp(u)
+        if out is None:
+            out = torch.empty_like(u)
+        self._check(self._lib.apply_F(self._h, _ptr(u, self.ncell, "u", nc),
+                                      _ptr(out, self.ncell, "out", nc), nc))
+        return out
+
+    def rkl2_step(self, u, dt, s=0) -> int:
+        self._sync_stream()
+        nc = self._ncomp(u)
+        used = ctypes.c_int()
+        self._check(self._lib.rkl2_step(self._h, _ptr(u, self.ncell, "u", nc), nc, float(dt),
+                                        int(s), ctypes.byref(used)))
+        return used.value
+
+    def be_pcg_solve(self, u_n, x, dt, pc=PC_JACOBI, block=(8, 8, 8), rtol=1e-8, maxit=10000,
+                     allow_not_converged=False):
+        self._sync_stream()
+        n = self.ncell
+        blk = (ctypes.c_int * 3)(*block)
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        st = self._lib.be_pcg_solve(self._h, _ptr(u_n, n, "u_n"), _ptr(x, n, "x"), float(dt),
+                                    int(pc), blk, float(rtol), int(maxit), ctypes.byref(it),
+                                    ctypes.byref(rel))
+        self._check(st, (STS_OK, STS_NOT_CONVERGED) if allow_not_converged else (STS_OK,))
+        return it.value, rel.value, st
+
+    def be_residual(self, u_n, x, dt) -> float:
+        self._sync_stream()
+        n = self.ncell
+        rel = ctypes.c_double()
+        self._check(self._lib.sts_be_residual(self._h, _ptr(u_n, n, "u_n"), _ptr(x, n, "x"),
+                                              float(dt), ctypes.byref(rel)))
+        return rel.value
+
+
+# Module-level names of the C ABI (same names, Python arguments).
+def sts_create(coord, f0, f1, f2, bc=SHELL_BC) -> Context:
+    return Context(coord, f0, f1, f2, bc)
+
+
+def sts_destroy(ctx: Context):
+    ctx.close()
+
+
+def sts_set_spitzer(ctx: Context, T, kappa0, b0, b1, b2):
+    ctx.set_spitzer(T, kappa0, b0, b1, b2)
+
+
+def sts_set_isotropic(ctx: Context, nu):
+    ctx.set_isotropic(nu)
+
+
+def sts_set_dirichlet(ctx: Context, side, values=None, value=0.0):
+    ctx.set_dirichlet(side, values, value)
+
+
+def sts_dt_euler(ctx: Context) -> float:
+    return ctx.dt_euler()
+
+
+def apply_F(ctx: Context, u, out=None):
+    return ctx.apply_F(u, out)
+
+
+def rkl2_step(ctx: Context, u, dt, s=0) -> int:
+    return ctx.rkl2_step(u, dt, s)
+
+
+def be_pcg_solve(ctx: Context, u_n, x, dt, pc=PC_JACOBI, block=(8, 8, 8), rtol=1e-8,
+                 maxit=10000, allow_not_converged=False):
+    return ctx.be_pcg_solve(u_n, x, dt, pc, block, rtol, maxit, allow_not_converged)
+
+
+def sts_be_residual(ctx: Context, u_n, x, dt) -> float:
+    return ctx.be_residual(u_n, x, dt)

@@ -1,0 +1,288 @@
+// Device helpers: grid indexing, separable geometry and the 19-point
+// finite-volume operator of the lagged conduction term.
+//
+// The operator is S u = -dE/du of the discrete energy
+//   E(u) = 1/2 sum_faces w_f (u_c' - u_c)^2 + sum_edges K_e X_e Y_e
+//          + 1/2 sum_Dirichlet faces w_b (u_b - u_c)^2,
+// where an edge in the (a, b) plane with origin cell e00 joins the cells
+// e00, e10 = e00 + e_a, e01 = e00 + e_b, e11 = e00 + e_a + e_b, and
+//   X = 1/2 [(u10 - u00)/dl_a(e00) + (u11 - u01)/dl_a(e01)]
+//   Y = 1/2 [(u01 - u00)/dl_b(e00) + (u11 - u10)/dl_b(e10)].
+// This is the cell-centred reading of the 19-point anisotropic conduction
+// stencil (the paper's operators have p = 19 nonzeros per row, Appendix B);
+// differentiating E gives, for the cell at role (p, q) of an edge,
+//   (S u)_c += K/2 [ s_a Y / dl_a(face of c) + s_b X / dl_b(face of c) ],
+// s_a = +1 if p = 0 else -1, s_b = +1 if q = 0 else -1.
+#pragma once
+
+#include "sts_internal.h"
+
+namespace sts {
+
+struct Nb {
+  int m, p;    // index of the -1 / +1 neighbour (clamped into range when absent)
+  bool hm, hp; // neighbour exists
+};
+
+__device__ __forceinline__ Nb nbr(int i, int n, int per) {
+  Nb r;
+  r.m = i - 1;
+  r.p = i + 1;
+  r.hm = true;
+  r.hp = true;
+  if (r.m < 0) {
+    if (per) r.m = n - 1;
+    else { r.m = 0; r.hm = false; }
+  }
+  if (r.p >= n) {
+    if (per) r.p = 0;
+    else { r.p = n - 1; r.hp = false; }
+  }
+  return r;
+}
+
+__device__ __forceinline__ double T0(const Grid &g, int t, int i) { return g.t0[t * g.n0 + i]; }
+__device__ __forceinline__ double T1(const Grid &g, int t, int j) { return g.t1[t * g.n1 + j]; }
+__device__ __forceinline__ double T2(const Grid &g, int t, int k) { return g.t2[t * g.n2 + k]; }
+
+__device__ __forceinline__ double vol(const Grid &g, int i, int j, int k) {
+  return T0(g, T_V0, i) * T1(g, T_V1, j) * T2(g, T_V2, k);
+}
+__device__ __forceinline__ double il0(const Grid &g, int i) { return T0(g, T_IL00, i); }
+__device__ __forceinline__ double il1(const Grid &g, int i, int j) {
+  return T0(g, T_IL10, i) * T1(g, T_IL11, j);
+}
+__device__ __forceinline__ double il2(const Grid &g, int i, int j, int k) {
+  return T0(g, T_IL20, i) * T1(g, T_IL21, j) * T2(g, T_IL22, k);
+}
+__device__ __forceinline__ double area0(const Grid &g, int i, int j, int k) {
+  return T0(g, T_A00, i) * T1(g, T_A01, j) * T2(g, T_A02, k);
+}
+__device__ __forceinline__ double area1(const Grid &g, int i, int j, int k) {
+  return T0(g, T_A10, i) * T1(g, T_A11, j) * T2(g, T_A12, k);
+}
+__device__ __forceinline__ double area2(const Grid &g, int i, int j, int k) {
+  return T0(g, T_A20, i) * T1(g, T_A21, j) * T2(g, T_A22, k);
+}
+
+__device__ __forceinline__ int lin(const Grid &g, int i, int j, int k) {
+  return (i * g.n1 + j) * g.n2 + k;
+}
+
+// Geometry of one edge touching cell (i, j, k), the cell being at role (p, q).
+struct EdgeGeo {
+  int e00;        // linear index of the edge origin (valid when ex)
+  bool ex;        // the edge exists (all four cells in the domain)
+  double ia0, ia1, ib0, ib1;  // 1/dl_a(e00), 1/dl_a(e01), 1/dl_b(e00), 1/dl_b(e10)
+};
+
+// PLANE 0: (a, b) = (0, 1); PLANE 1: (0, 2); PLANE 2: (1, 2)
+template <int PLANE>
+__device__ __forceinline__ EdgeGeo edge_geo(const Grid &g, int i, int j, int k, const Nb &A,
+                                            const Nb &B, const Nb &C, int p, int q) {
+  EdgeGeo e;
+  if (PLANE == 0) {
+    const int ei = p ? A.m : i, e10i = p ? i : A.p, ej = q ? B.m : j;
+    e.ex = (p ? A.hm : A.hp) && (q ? B.hm : B.hp);
+    e.ia0 = e.ia1 = il0(g, ei);
+    e.ib0 = il1(g, ei, ej);
+    e.ib1 = il1(g, e10i, ej);
+    e.e00 = lin(g, ei, ej, k);
+  } else if (PLANE == 1) {
+    const int ei = p ? A.m : i, e10i = p ? i : A.p, ek = q ? C.m : k;
+    e.ex = (p ? A.hm : A.hp) && (q ? C.hm : C.hp);
+    e.ia0 = e.ia1 = il0(g, ei);
+    e.ib0 = il2(g, ei, j, ek);
+    e.ib1 = il2(g, e10i, j, ek);
+    e.e00 = lin(g, ei, j, ek);
+  } else {
+    const int ej = p ? B.m : j, e10j = p ? j : B.p, ek = q ? C.m : k;
+    e.ex = (p ? B.hm : B.hp) && (q ? C.hm : C.hp);
+    e.ia0 = e.ia1 = il1(g, i, ej);
+    e.ib0 = il2(g, i, ej, ek);
+    e.ib1 = il2(g, i, e10j, ek);
+    e.e00 = lin(g, i, ej, ek);
+  }
+  return e;
+}
+
+// Contribution of one edge to (S u)_c for the cell at role (p, q).
+__device__ __forceinline__ double edge_term(double K, double u00, double u10, double u01,
+                                            double u11, const EdgeGeo &e, int p, int q) {
+  const double X = 0.5 * ((u10 - u00) * e.ia0 + (u11 - u01) * e.ia1);
+  const double Y = 0.5 * ((u01 - u00) * e.ib0 + (u11 - u10) * e.ib1);
+  const double ya = (q ? e.ia1 : e.ia0) * Y;
+  const double xb = (p ? e.ib1 : e.ib0) * X;
+  return 0.5 * K * ((p ? -ya : ya) + (q ? -xb : xb));
+}
+
+// A source of stencil values: plain array read.
+struct ArrayField {
+  const double *__restrict__ u;
+  __device__ __forceinline__ double operator()(int idx) const { return u[idx]; }
+};
+
+// (S u)_c (+ g_c when WITH_G) for the 19-point conduction operator.
+template <bool WITH_G, class Field>
+__device__ __forceinline__ double s19(const Grid &g, const Coef &C, const Field &u, int i, int j,
+                                      int k) {
+  const Nb A = nbr(i, g.n0, g.per0), B = nbr(j, g.n1, g.per1), Cn = nbr(k, g.n2, g.per2);
+  const int c = lin(g, i, j, k);
+  const double u000 = u(c);
+  const double um00 = u(lin(g, A.m, j, k)), up00 = u(lin(g, A.p, j, k));
+  const double u0m0 = u(lin(g, i, B.m, k)), u0p0 = u(lin(g, i, B.p, k));
+  const double u00m = u(lin(g, i, j, Cn.m)), u00p = u(lin(g, i, j, Cn.p));
+  const double umm0 = u(lin(g, A.m, B.m, k)), ump0 = u(lin(g, A.m, B.p, k));
+  const double upm0 = u(lin(g, A.p, B.m, k)), upp0 = u(lin(g, A.p, B.p, k));
+  const double um0m = u(lin(g, A.m, j, Cn.m)), um0p = u(lin(g, A.m, j, Cn.p));
+  const double up0m = u(lin(g, A.p, j, Cn.m)), up0p = u(lin(g, A.p, j, Cn.p));
+  const double u0mm = u(lin(g, i, B.m, Cn.m)), u0mp = u(lin(g, i, B.m, Cn.p));
+  const double u0pm = u(lin(g, i, B.p, Cn.m)), u0pp = u(lin(g, i, B.p, Cn.p));
+
+  double acc = 0.0;
+  // faces (weights are zero on faces that do not exist on the + side)
+  acc += C.w0[c] * (up00 - u000);
+  if (A.hm) acc += C.w0[lin(g, A.m, j, k)] * (um00 - u000);
+  acc += C.w1[c] * (u0p0 - u000);
+  if (B.hm) acc += C.w1[lin(g, i, B.m, k)] * (u0m0 - u000);
+  acc += C.w2[c] * (u00p - u000);
+  if (Cn.hm) acc += C.w2[lin(g, i, j, Cn.m)] * (u00m - u000);
+
+  // edges, plane (0, 1)
+  {
+    EdgeGeo e;
+    e = edge_geo<0>(g, i, j, k, A, B, Cn, 0, 0);
+    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, u000, up00, u0p0, upp0, e, 0, 0);
+    e = edge_geo<0>(g, i, j, k, A, B, Cn, 1, 0);
+    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, um00, u000, ump0, u0p0, e, 1, 0);
+    e = edge_geo<0>(g, i, j, k, A, B, Cn, 0, 1);
+    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, u0m0, upm0, u000, up00, e, 0, 1);
+    e = edge_geo<0>(g, i, j, k, A, B, Cn, 1, 1);
+    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, umm0, u0m0, um00, u000, e, 1, 1);
+  }
+  // plane (0, 2)
+  {
+    EdgeGeo e;
+    e = edge_geo<1>(g, i, j, k, A, B, Cn, 0, 0);
+    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, u000, up00, u00p, up0p, e, 0, 0);
+    e = edge_geo<1>(g, i, j, k, A, B, Cn, 1, 0);
+    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, um00, u000, um0p, u00p, e, 1, 0);
+    e = edge_geo<1>(g, i, j, k, A, B, Cn, 0, 1);
+    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, u00m, up0m, u000, up00, e, 0, 1);
+    e = edge_geo<1>(g, i, j, k, A, B, Cn, 1, 1);
+    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, um0m, u00m, um00, u000, e, 1, 1);
+  }
+  // plane (1, 2)
+  {
+    EdgeGeo e;
+    e = edge_geo<2>(g, i, j, k, A, B, Cn, 0, 0);
+    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u000, u0p0, u00p, u0pp, e, 0, 0);
+    e = edge_geo<2>(g, i, j, k, A, B, Cn, 1, 0);
+    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u0m0, u000, u0mp, u00p, e, 1, 0);
+    e = edge_geo<2>(g, i, j, k, A, B, Cn, 0, 1);
+    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u00m, u0pm, u000, u0p0, e, 0, 1);
+    e = edge_geo<2>(g, i, j, k, A, B, Cn, 1, 1);
+    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u0mm, u00m, u0m0, u000, e, 1, 1);
+  }
+  // Dirichlet faces on axis 0
+  if (g.dir_lo && i == 0) {
+    const int b = j * g.n2 + k;
+    acc += WITH_G ? C.wb_lo[b] * (C.ub_lo[b] - u000) : -C.wb_lo[b] * u000;
+  }
+  if (g.dir_hi && i == g.n0 - 1) {
+    const int b = j * g.n2 + k;
+    acc += WITH_G ? C.wb_hi[b] * (C.ub_hi[b] - u000) : -C.wb_hi[b] * u000;
+  }
+  return acc;
+}
+
+// (S u)_c (+ g_c) for the isotropic 7-point operator nu * Laplacian.
+template <bool WITH_G, class Field>
+__device__ __forceinline__ double s7(const Grid &g, const Coef &C, const Field &u, int i, int j,
+                                     int k) {
+  const Nb A = nbr(i, g.n0, g.per0), B = nbr(j, g.n1, g.per1), Cn = nbr(k, g.n2, g.per2);
+  const int c = lin(g, i, j, k);
+  const double u000 = u(c);
+  double acc = 0.0;
+  acc += area0(g, i, j, k) * il0(g, i) * (u(lin(g, A.p, j, k)) - u000);
+  if (A.hm) acc += area0(g, A.m, j, k) * il0(g, A.m) * (u(lin(g, A.m, j, k)) - u000);
+  acc += area1(g, i, j, k) * il1(g, i, j) * (u(lin(g, i, B.p, k)) - u000);
+  if (B.hm) acc += area1(g, i, B.m, k) * il1(g, i, B.m) * (u(lin(g, i, B.m, k)) - u000);
+  acc += area2(g, i, j, k) * il2(g, i, j, k) * (u(lin(g, i, j, Cn.p)) - u000);
+  if (Cn.hm) acc += area2(g, i, j, Cn.m) * il2(g, i, j, Cn.m) * (u(lin(g, i, j, Cn.m)) - u000);
+  acc *= C.nu;
+  if (g.dir_lo && i == 0) {
+    const int b = j * g.n2 + k;
+    acc += WITH_G ? C.wb_lo[b] * (C.ub_lo[b] - u000) : -C.wb_lo[b] * u000;
+  }
+  if (g.dir_hi && i == g.n0 - 1) {
+    const int b = j * g.n2 + k;
+    acc += WITH_G ? C.wb_hi[b] * (C.ub_hi[b] - u000) : -C.wb_hi[b] * u000;
+  }
+  return acc;
+}
+
+// Row c of S as a 3x3x3 array row[(dx+1)*9 + (dy+1)*3 + (dz+1)] = S[c, c+d]
+// (only the 19 stencil entries can be non-zero).  OP: 1 conduction, 2 isotropic.
+__device__ __forceinline__ void add_edge_row(double *row, int sa, int sb, double K,
+                                             const EdgeGeo &e, int p, int q) {
+  const double am = (p ? 0.5 : -0.5) * (q ? e.ia1 : e.ia0);
+  const double bm = (q ? 0.5 : -0.5) * (p ? e.ib1 : e.ib0);
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      const double an = (pp ? 0.5 : -0.5) * (qq ? e.ia1 : e.ia0);
+      const double bn = (qq ? 0.5 : -0.5) * (pp ? e.ib1 : e.ib0);
+      row[13 + (pp - p) * sa + (qq - q) * sb] -= K * (am * bn + bm * an);
+    }
+}
+
+template <int OP>
+__device__ __forceinline__ void row27(const Grid &g, const Coef &C, int i, int j, int k,
+                                      double *row) {
+#pragma unroll
+  for (int t = 0; t < 27; ++t) row[t] = 0.0;
+  const Nb A = nbr(i, g.n0, g.per0), B = nbr(j, g.n1, g.per1), Cn = nbr(k, g.n2, g.per2);
+  const int c = lin(g, i, j, k);
+  double wp0, wm0, wp1, wm1, wp2, wm2;
+  if (OP == OP_SPITZER) {
+    wp0 = C.w0[c];
+    wm0 = A.hm ? C.w0[lin(g, A.m, j, k)] : 0.0;
+    wp1 = C.w1[c];
+    wm1 = B.hm ? C.w1[lin(g, i, B.m, k)] : 0.0;
+    wp2 = C.w2[c];
+    wm2 = Cn.hm ? C.w2[lin(g, i, j, Cn.m)] : 0.0;
+  } else {
+    wp0 = C.nu * area0(g, i, j, k) * il0(g, i);
+    wm0 = A.hm ? C.nu * area0(g, A.m, j, k) * il0(g, A.m) : 0.0;
+    wp1 = C.nu * area1(g, i, j, k) * il1(g, i, j);
+    wm1 = B.hm ? C.nu * area1(g, i, B.m, k) * il1(g, i, B.m) : 0.0;
+    wp2 = C.nu * area2(g, i, j, k) * il2(g, i, j, k);
+    wm2 = Cn.hm ? C.nu * area2(g, i, j, Cn.m) * il2(g, i, j, Cn.m) : 0.0;
+  }
+  row[13 + 9] += wp0;
+  row[13 - 9] += wm0;
+  row[13 + 3] += wp1;
+  row[13 - 3] += wm1;
+  row[13 + 1] += wp2;
+  row[13 - 1] += wm2;
+  row[13] -= wp0 + wm0 + wp1 + wm1 + wp2 + wm2;
+  if (OP == OP_SPITZER) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        EdgeGeo e = edge_geo<0>(g, i, j, k, A, B, Cn, p, q);
+        if (e.ex) add_edge_row(row, 9, 3, C.k01[e.e00], e, p, q);
+        e = edge_geo<1>(g, i, j, k, A, B, Cn, p, q);
+        if (e.ex) add_edge_row(row, 9, 1, C.k02[e.e00], e, p, q);
+        e = edge_geo<2>(g, i, j, k, A, B, Cn, p, q);
+        if (e.ex) add_edge_row(row, 3, 1, C.k12[e.e00], e, p, q);
+      }
+  }
+  if (g.dir_lo && i == 0) row[13] -= C.wb_lo[j * g.n2 + k];
+  if (g.dir_hi && i == g.n0 - 1) row[13] -= C.wb_hi[j * g.n2 + k];
+}
+
+}  // namespace sts

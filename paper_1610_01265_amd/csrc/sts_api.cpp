@@ -1,0 +1,566 @@
+// Host side of the C ABI declared in include/sts.h: context management, the
+// separable geometry tables, argument checking and the launch sequences of
+// RKL2 and BE+PCG.  No arithmetic of the method runs here apart from the
+// 1D geometry tables, the RKL2 stage coefficients and the stage count.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "sts_internal.h"
+
+using namespace sts;
+
+sts::Grid sts_ctx::grid() const {
+  Grid g;
+  g.n0 = n0;
+  g.n1 = n1;
+  g.n2 = n2;
+  g.per0 = bc[0] == STS_BC_PERIODIC;
+  g.per1 = bc[2] == STS_BC_PERIODIC;
+  g.per2 = bc[4] == STS_BC_PERIODIC;
+  g.dir_lo = bc[0] == STS_BC_DIRICHLET;
+  g.dir_hi = bc[1] == STS_BC_DIRICHLET;
+  g.t0 = d_t0;
+  g.t1 = d_t1;
+  g.t2 = d_t2;
+  g.ab_lo = ab_lo;
+  g.ab_hi = ab_hi;
+  g.db_lo = db_lo;
+  g.db_hi = db_hi;
+  return g;
+}
+
+sts::Coef sts_ctx::coef() const {
+  Coef c;
+  const long long n = ncell;
+  c.w0 = d_w;
+  c.w1 = d_w ? d_w + n : nullptr;
+  c.w2 = d_w ? d_w + 2 * n : nullptr;
+  c.k01 = d_w ? d_w + 3 * n : nullptr;
+  c.k02 = d_w ? d_w + 4 * n : nullptr;
+  c.k12 = d_w ? d_w + 5 * n : nullptr;
+  const long long nb = (long long)n1 * n2;
+  c.wb_lo = d_bnd;
+  c.wb_hi = d_bnd + nb;
+  c.ub_lo = d_bnd + 2 * nb;
+  c.ub_hi = d_bnd + 3 * nb;
+  c.nu = nu;
+  return c;
+}
+
+namespace {
+
+#define FAIL(code, msg)     \
+  do {                      \
+    ctx->err = (msg);       \
+    return (code);          \
+  } while (0)
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+      return STS_EHIP;                                                            \
+    }                                                                             \
+  } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+sts_status dalloc(sts_ctx *ctx, void **p, size_t bytes) {
+  if (*p) return STS_OK;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    ctx->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
+    return STS_ENOMEM;
+  }
+  return STS_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+bool finite_increasing(const double *f, int n) {
+  for (int m = 0; m <= n; ++m)
+    if (!std::isfinite(f[m])) return false;
+  for (int m = 0; m < n; ++m)
+    if (!(f[m + 1] > f[m])) return false;
+  return true;
+}
+
+// centre-to-centre distance across the +face of each cell (0 where absent)
+std::vector<double> inv_gaps(const double *f, int n, bool periodic) {
+  std::vector<double> c(n), ig(n, 0.0);
+  for (int m = 0; m < n; ++m) c[m] = 0.5 * (f[m] + f[m + 1]);
+  for (int m = 0; m + 1 < n; ++m) ig[m] = 1.0 / (c[m + 1] - c[m]);
+  if (periodic) ig[n - 1] = 1.0 / (c[0] + (f[n] - f[0]) - c[n - 1]);
+  return ig;
+}
+
+// RKL2 stage count: least s >= 2 with s^2 + s - 2 >= 4 dt/dt_E (Eq. rkl2_s)
+int stage_count(double ratio) {
+  int s = (int)std::ceil((std::sqrt(9.0 + 16.0 * ratio) - 1.0) / 2.0);
+  if (s < 2) s = 2;
+  while (s - 1 >= 2 && (double)(s - 1) * (s - 1) + (s - 1) - 2.0 >= 4.0 * ratio) --s;
+  while ((double)s * s + s - 2.0 < 4.0 * ratio) ++s;
+  return s;
+}
+
+constexpr int kMaxStages = 1 << 20;
+constexpr int kPollEvery = 8;  // PCG iterations enqueued between host polls
+
+}  // namespace
+
+extern "C" {
+
+sts_status sts_create(sts_ctx **out, int coord, int n0, int n1, int n2, const double *f0,
+                      const double *f1, const double *f2, const int bc[6], void *stream) {
+  if (!out) return STS_EINVAL;
+  *out = nullptr;
+  auto *ctx = new sts_ctx();
+  auto bad = [&](const char *m) {
+    std::fprintf(stderr, "sts_create: %s\n", m);
+    delete ctx;
+    return STS_EINVAL;
+  };
+  if (coord != STS_SPHERICAL && coord != STS_CARTESIAN) return bad("unknown coordinate system");
+  if (n0 < 1 || n1 < 1 || n2 < 1) return bad("grid dimensions must be >= 1");
+  const long long ncell = (long long)n0 * n1 * n2;
+  if (ncell > (long long)std::numeric_limits<int>::max() / 2) return bad("grid too large");
+  if (!f0 || !f1 || !f2 || !bc) return bad("null face array or bc");
+  if (!finite_increasing(f0, n0) || !finite_increasing(f1, n1) || !finite_increasing(f2, n2))
+    return bad("face coordinates must be finite and strictly increasing");
+  for (int s = 0; s < 6; ++s)
+    if (bc[s] != STS_BC_ZEROFLUX && bc[s] != STS_BC_DIRICHLET && bc[s] != STS_BC_PERIODIC)
+      return bad("unknown boundary condition");
+  const int nn[3] = {n0, n1, n2};
+  for (int a = 0; a < 3; ++a) {
+    const bool pl = bc[2 * a] == STS_BC_PERIODIC, ph = bc[2 * a + 1] == STS_BC_PERIODIC;
+    if (pl != ph) return bad("periodic must be set on both sides of an axis");
+    if (pl && nn[a] < 3) return bad("a periodic axis needs at least 3 cells");
+    if (a > 0 && (bc[2 * a] == STS_BC_DIRICHLET || bc[2 * a + 1] == STS_BC_DIRICHLET))
+      return bad("Dirichlet boundaries are supported on axis 0 only");
+  }
+  if (coord == STS_SPHERICAL) {
+    if (!(f0[0] > 0.0)) return bad("spherical radii must be positive");
+    if (!(f1[0] > 0.0) || !(f1[n1] < M_PI)) return bad("colatitudes must lie in (0, pi)");
+  }
+  ctx->coord = coord;
+  ctx->n0 = n0;
+  ctx->n1 = n1;
+  ctx->n2 = n2;
+  ctx->ncell = ncell;
+  std::memcpy(ctx->bc, bc, sizeof(ctx->bc));
+  ctx->stream = (hipStream_t)stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return STS_EHIP;
+  }
+
+  // --- separable geometry tables ---
+  std::vector<double> t0((size_t)NT0 * n0), t1((size_t)NT1 * n1), t2((size_t)NT2 * n2);
+  const bool per0 = bc[0] == STS_BC_PERIODIC, per1 = bc[2] == STS_BC_PERIODIC,
+             per2 = bc[4] == STS_BC_PERIODIC;
+  const std::vector<double> ig0 = inv_gaps(f0, n0, per0), ig1 = inv_gaps(f1, n1, per1),
+                            ig2 = inv_gaps(f2, n2, per2);
+  for (int i = 0; i < n0; ++i) {
+    const double a = f0[i], b = f0[i + 1], c = 0.5 * (a + b), d = b - a;
+    double *T = t0.data();
+    if (coord == STS_SPHERICAL) {
+      T[T_V0 * n0 + i] = (b * b * b - a * a * a) / 3.0;
+      T[T_A00 * n0 + i] = b * b;
+      T[T_A10 * n0 + i] = 0.5 * (b * b - a * a);
+      T[T_A20 * n0 + i] = 0.5 * (b * b - a * a);
+      T[T_IL10 * n0 + i] = 1.0 / c;
+      T[T_IL20 * n0 + i] = 1.0 / c;
+    } else {
+      T[T_V0 * n0 + i] = d;
+      T[T_A00 * n0 + i] = 1.0;
+      T[T_A10 * n0 + i] = d;
+      T[T_A20 * n0 + i] = d;
+      T[T_IL10 * n0 + i] = 1.0;
+      T[T_IL20 * n0 + i] = 1.0;
+    }
+    T[T_IL00 * n0 + i] = ig0[i];
+  }
+  for (int j = 0; j < n1; ++j) {
+    const double a = f1[j], b = f1[j + 1], c = 0.5 * (a + b), d = b - a;
+    double *T = t1.data();
+    if (coord == STS_SPHERICAL) {
+      T[T_V1 * n1 + j] = std::cos(a) - std::cos(b);
+      T[T_A01 * n1 + j] = std::cos(a) - std::cos(b);
+      T[T_A11 * n1 + j] = std::sin(b);
+      T[T_A21 * n1 + j] = d;
+      T[T_IL21 * n1 + j] = 1.0 / std::sin(c);
+    } else {
+      T[T_V1 * n1 + j] = d;
+      T[T_A01 * n1 + j] = d;
+      T[T_A11 * n1 + j] = 1.0;
+      T[T_A21 * n1 + j] = d;
+      T[T_IL21 * n1 + j] = 1.0;
+    }
+    T[T_IL11 * n1 + j] = ig1[j];
+  }
+  for (int k = 0; k < n2; ++k) {
+    const double d = f2[k + 1] - f2[k];
+    double *T = t2.data();
+    T[T_V2 * n2 + k] = d;
+    T[T_A02 * n2 + k] = d;
+    T[T_A12 * n2 + k] = d;
+    T[T_A22 * n2 + k] = 1.0;
+    T[T_IL22 * n2 + k] = ig2[k];
+  }
+  if (coord == STS_SPHERICAL) {
+    ctx->ab_lo = f0[0] * f0[0];
+    ctx->ab_hi = f0[n0] * f0[n0];
+  } else {
+    ctx->ab_lo = ctx->ab_hi = 1.0;
+  }
+  ctx->db_lo = 0.5 * (f0[0] + f0[1]) - f0[0];
+  ctx->db_hi = f0[n0] - 0.5 * (f0[n0 - 1] + f0[n0]);
+
+  auto cleanup = [&](sts_status st) {
+    sts_destroy(ctx);
+    return st;
+  };
+  sts_status st;
+  const long long nb = (long long)n1 * n2;
+  if ((st = dalloc(ctx, (void **)&ctx->d_t0, t0.size() * 8)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_t1, t1.size() * 8)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_t2, t2.size() * 8)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_bnd, 4 * nb * 8)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_flag, 64)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_tmp, 64)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_sc, sizeof(PcgScalars))))
+    return cleanup(st);
+  if (hipHostMalloc(&ctx->h_pin, 256, hipHostMallocDefault) != hipSuccess) {
+    ctx->h_pin = nullptr;
+    return cleanup(STS_ENOMEM);
+  }
+  if (hipMemcpyAsync(ctx->d_t0, t0.data(), t0.size() * 8, hipMemcpyHostToDevice, ctx->stream) ||
+      hipMemcpyAsync(ctx->d_t1, t1.data(), t1.size() * 8, hipMemcpyHostToDevice, ctx->stream) ||
+      hipMemcpyAsync(ctx->d_t2, t2.data(), t2.size() * 8, hipMemcpyHostToDevice, ctx->stream))
+    return cleanup(STS_EHIP);
+  launch_fill(ctx, ctx->d_bnd, 4 * nb, 0.0);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(STS_EHIP);
+  *out = ctx;
+  return STS_OK;
+}
+
+sts_status sts_destroy(sts_ctx *ctx) {
+  if (!ctx) return STS_EINVAL;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  dfree(ctx->d_t0);
+  dfree(ctx->d_t1);
+  dfree(ctx->d_t2);
+  dfree(ctx->d_w);
+  dfree(ctx->d_sdiag);
+  dfree(ctx->d_bnd);
+  dfree(ctx->d_rk);
+  dfree(ctx->d_pcg);
+  dfree(ctx->d_red);
+  dfree(ctx->d_sc);
+  dfree(ctx->d_ilu);
+  dfree(ctx->d_flag);
+  dfree(ctx->d_tmp);
+  if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
+  delete ctx;
+  return STS_OK;
+}
+
+sts_status sts_set_stream(sts_ctx *ctx, void *stream) {
+  if (!ctx) return STS_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  return STS_OK;
+}
+
+const char *sts_last_error(const sts_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+long long sts_num_cells(const sts_ctx *ctx) { return ctx ? ctx->ncell : 0; }
+
+static sts_status refresh_dirichlet_values(sts_ctx *ctx) {
+  const long long nb = (long long)ctx->n1 * ctx->n2;
+  for (int side = 0; side < 2; ++side)
+    if (!ctx->ub_array[side]) launch_fill(ctx, ctx->d_bnd + (2 + side) * nb, nb, ctx->ub_const[side]);
+  LAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status sts_set_spitzer(sts_ctx *ctx, const double *T, double kappa0, const double *b0,
+                           const double *b1, const double *b2) {
+  if (!ctx) return STS_EINVAL;
+  if (!T || !b0 || !b1 || !b2) FAIL(STS_EINVAL, "sts_set_spitzer: null field");
+  if (!(kappa0 > 0.0) || !std::isfinite(kappa0)) FAIL(STS_EINVAL, "kappa0 must be finite, > 0");
+  sts_status st;
+  if ((st = dalloc(ctx, (void **)&ctx->d_w, 6 * ctx->ncell * 8)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_sdiag, ctx->ncell * 8)))
+    return st;
+  HIPCHK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+  launch_check_spitzer(ctx, T, b0, b1, b2, ctx->d_flag);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(ctx->h_pin, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (*(int *)ctx->h_pin) FAIL(STS_EINVAL, "sts_set_spitzer: T must be finite and > 0, b finite");
+  if ((st = refresh_dirichlet_values(ctx))) return st;
+  ctx->op = OP_SPITZER;
+  ctx->nu = 0.0;
+  launch_spitzer_coef(ctx, T, kappa0, b0, b1, b2);
+  LAUNCHCHK();
+  launch_sdiag(ctx);
+  LAUNCHCHK();
+  ctx->dt_euler = -1.0;
+  return STS_OK;
+}
+
+sts_status sts_set_isotropic(sts_ctx *ctx, double nu) {
+  if (!ctx) return STS_EINVAL;
+  if (!(nu > 0.0) || !std::isfinite(nu)) FAIL(STS_EINVAL, "nu must be finite and > 0");
+  sts_status st;
+  if ((st = dalloc(ctx, (void **)&ctx->d_sdiag, ctx->ncell * 8))) return st;
+  if ((st = refresh_dirichlet_values(ctx))) return st;
+  ctx->op = OP_ISOTROPIC;
+  ctx->nu = nu;
+  launch_dirichlet_weights(ctx);
+  LAUNCHCHK();
+  launch_sdiag(ctx);
+  LAUNCHCHK();
+  ctx->dt_euler = -1.0;
+  return STS_OK;
+}
+
+sts_status sts_set_dirichlet(sts_ctx *ctx, int side, const double *values, double value) {
+  if (!ctx) return STS_EINVAL;
+  if (side != 0 && side != 1) FAIL(STS_EINVAL, "side must be 0 or 1");
+  if (!values && !std::isfinite(value)) FAIL(STS_EINVAL, "Dirichlet value must be finite");
+  const long long nb = (long long)ctx->n1 * ctx->n2;
+  double *dst = ctx->d_bnd + (2 + side) * nb;
+  if (values) {
+    HIPCHK(hipMemcpyAsync(dst, values, nb * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->ub_array[side] = true;
+  } else {
+    ctx->ub_const[side] = value;
+    ctx->ub_array[side] = false;
+    launch_fill(ctx, dst, nb, value);
+    LAUNCHCHK();
+  }
+  return STS_OK;
+}
+
+static sts_status ensure_red(sts_ctx *ctx, int need) {
+  if (ctx->red_cap >= need) return STS_OK;
+  dfree(ctx->d_red);
+  ctx->red_cap = 0;
+  sts_status st = dalloc(ctx, (void **)&ctx->d_red, (size_t)3 * need * 8);
+  if (st) return st;
+  ctx->red_cap = need;
+  return STS_OK;
+}
+
+sts_status sts_dt_euler(sts_ctx *ctx, double *dt_e) {
+  if (!ctx || !dt_e) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (ctx->dt_euler > 0) {
+    *dt_e = ctx->dt_euler;
+    return STS_OK;
+  }
+  const int np = gershgorin_parts(ctx);
+  sts_status st;
+  if ((st = ensure_red(ctx, std::max(np, pcg_parts(ctx))))) return st;
+  launch_gershgorin(ctx, ctx->d_red, np);
+  LAUNCHCHK();
+  std::vector<double> h(np);
+  HIPCHK(hipMemcpyAsync(h.data(), ctx->d_red, (size_t)np * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double m = 0.0;
+  for (double v : h) m = std::max(m, v);
+  if (!(m > 0.0) || !std::isfinite(m)) FAIL(STS_EINVAL, "operator has no finite nonzero rows");
+  ctx->dt_euler = 2.0 / m;
+  *dt_e = ctx->dt_euler;
+  return STS_OK;
+}
+
+sts_status apply_F(sts_ctx *ctx, const double *u, double *Fu, int ncomp) {
+  if (!ctx) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (!u || !Fu || u == Fu) FAIL(STS_EINVAL, "apply_F: null or aliased arrays");
+  if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, "apply_F: ncomp must be in [1, 16]");
+  launch_stage(ctx, 0, ncomp, u, nullptr, nullptr, nullptr, Fu, 0, 0, 0, 0);
+  LAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used) {
+  if (!ctx) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (!u) FAIL(STS_EINVAL, "rkl2_step: null u");
+  if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, "rkl2_step: ncomp must be in [1, 16]");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "rkl2_step: dt must be finite, > 0");
+  if (s <= 0) {
+    double dte;
+    sts_status st = sts_dt_euler(ctx, &dte);
+    if (st) return st;
+    const double ratio = dt / dte;
+    if (!(ratio < 0.25 * kMaxStages * (double)kMaxStages)) FAIL(STS_EINVAL, "dt too large");
+    s = stage_count(ratio);
+  }
+  if (s < 2 || s > kMaxStages) FAIL(STS_EINVAL, "rkl2_step: s must be >= 2");
+  const long long n = ctx->ncell * ncomp;
+  if (ctx->rk_ncomp < ncomp) {
+    dfree(ctx->d_rk);
+    ctx->rk_ncomp = 0;
+    sts_status st = dalloc(ctx, (void **)&ctx->d_rk, (size_t)3 * n * 8);
+    if (st) return st;
+    ctx->rk_ncomp = ncomp;
+  }
+  double *F0 = ctx->d_rk, *Ya = ctx->d_rk + n, *Yb = ctx->d_rk + 2 * n;
+  // stage coefficients (Sec. 3): b_k, mu_k, nu_k, mu~_k, gamma~_k
+  const double ss = (double)s * s + s - 2.0;
+  auto bk = [](int k) { return k <= 2 ? 1.0 / 3.0 : ((double)k * k + k - 2.0) / (2.0 * k * (k + 1.0)); };
+  const double w1 = 4.0 / ss;
+  launch_stage(ctx, 1, ncomp, u, nullptr, u, F0, Ya, 0, 0, (w1 / 3.0) * dt, 0);
+  LAUNCHCHK();
+  for (int k = 2; k <= s; ++k) {
+    const double b = bk(k), b1 = bk(k - 1), b2 = bk(k - 2);
+    const double mu = (2.0 * k - 1.0) / k * b / b1;
+    const double nu = -(k - 1.0) / k * b / b2;
+    const double mut = 4.0 * (2.0 * k - 1.0) / (k * ss) * b / b1;
+    const double gt = -(1.0 - b1) * mut;
+    const double *ukm1 = ((k - 1) & 1) ? Ya : Yb;
+    const double *ukm2 = (k == 2) ? u : (((k - 2) & 1) ? Ya : Yb);
+    double *out = (k == s) ? u : ((k & 1) ? Ya : Yb);
+    launch_stage(ctx, 2, ncomp, ukm1, ukm2, u, F0, out, mu, nu, mut * dt, gt * dt);
+    LAUNCHCHK();
+  }
+  if (s_used) *s_used = s;
+  return STS_OK;
+}
+
+static sts_status pcg_workspace(sts_ctx *ctx, int pc, const int block[3], double **fac) {
+  const long long n = ctx->ncell;
+  sts_status st;
+  if ((st = dalloc(ctx, (void **)&ctx->d_pcg, (size_t)7 * n * 8))) return st;
+  int need = pcg_parts(ctx);
+  if (pc == STS_PC_BLOCK_ILU0) need = std::max(need, ilu_parts(ctx, block));
+  if ((st = ensure_red(ctx, need))) return st;
+  *fac = nullptr;
+  if (pc == STS_PC_BLOCK_ILU0) {
+    const long long need_f = (long long)ilu_nblocks(ctx, block) * 10 * block[0] * block[1] * block[2];
+    if (ctx->ilu_cap < need_f) {
+      dfree(ctx->d_ilu);
+      ctx->ilu_cap = 0;
+      if ((st = dalloc(ctx, (void **)&ctx->d_ilu, (size_t)need_f * 8))) return st;
+      ctx->ilu_cap = need_f;
+    }
+    *fac = ctx->d_ilu;
+  }
+  return STS_OK;
+}
+
+sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, int pc,
+                        const int block[3], double rtol, int maxit, int *iters, double *relres) {
+  if (!ctx) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (!u_n || !x || u_n == x) FAIL(STS_EINVAL, "be_pcg_solve: null or aliased u_n / x");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "be_pcg_solve: dt must be finite, > 0");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol)) FAIL(STS_EINVAL, "be_pcg_solve: bad rtol");
+  if (maxit < 0) FAIL(STS_EINVAL, "be_pcg_solve: maxit must be >= 0");
+  if (pc != STS_PC_JACOBI && pc != STS_PC_BLOCK_ILU0) FAIL(STS_EINVAL, "unknown preconditioner");
+  int blk[3] = {1, 1, 1};
+  if (pc == STS_PC_BLOCK_ILU0) {
+    if (!block) FAIL(STS_EINVAL, "block ILU0 needs block[3]");
+    for (int a = 0; a < 3; ++a) {
+      if (block[a] < 1 || block[a] > 8) FAIL(STS_EINVAL, "ILU0 block sizes must be in [1, 8]");
+      blk[a] = block[a];
+    }
+  }
+  double *fac;
+  sts_status st = pcg_workspace(ctx, pc, blk, &fac);
+  if (st) return st;
+  const long long n = ctx->ncell, cap = ctx->red_cap;
+  double *b = ctx->d_pcg, *invd = b + n, *r = b + 2 * n, *p0 = b + 3 * n, *p1 = b + 4 * n,
+         *y = b + 5 * n, *z = b + 6 * n;
+  double *part = ctx->d_red;
+  PcgScalars *sc = ctx->d_sc;
+  const bool ilu = pc == STS_PC_BLOCK_ILU0;
+
+  launch_be_rhs(ctx, u_n, dt, b, invd, part + 2 * cap);
+  LAUNCHCHK();
+  launch_residual_init(ctx, b, x, dt, invd, nullptr, r, nullptr, part);
+  LAUNCHCHK();
+  if (ilu) {
+    HIPCHK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+    launch_ilu_factor(ctx, dt, blk, fac, ctx->d_flag);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(ctx->h_pin, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (*(int *)ctx->h_pin) FAIL(STS_BREAKDOWN, "ILU0 breakdown: non-positive pivot");
+    launch_ilu_apply_init(ctx, blk, fac, r, z);
+    LAUNCHCHK();
+  }
+  launch_init_p(ctx, r, invd, ilu ? z : nullptr, p0, part + 2 * cap);
+  LAUNCHCHK();
+  launch_finalize_init3(ctx, part + cap, part, part + 2 * cap, sc, rtol, maxit);
+  LAUNCHCHK();
+
+  const int nb_parts = ilu ? ilu_parts(ctx, blk) : pass_b_parts(ctx);
+  PcgScalars *h = (PcgScalars *)ctx->h_pin;
+  double *pold = p0, *pnew = p1;
+  HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int it = 0; it < maxit && !h->done; ++it) {
+    launch_pass_a(ctx, dt, r, invd, ilu ? z : nullptr, pold, pnew, y, part, sc, it == 0);
+    launch_finalize_alpha(ctx, part, stencil_parts(ctx), sc);
+    if (ilu)
+      launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
+    else
+      launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, part, sc);
+    launch_finalize_beta(ctx, part, nb_parts, sc);
+    LAUNCHCHK();
+    std::swap(pold, pnew);
+    if ((it + 1) % kPollEvery == 0 || it + 1 == maxit) {
+      HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+  }
+  HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (iters) *iters = h->iters;
+  if (relres) *relres = h->bnorm2 > 0 ? std::sqrt(h->rnorm2 / h->bnorm2) : 0.0;
+  if (h->status == -4) FAIL(STS_BREAKDOWN, "PCG breakdown: p.Ap <= 0 or non-finite residual");
+  if (h->status == 1) return STS_OK;
+  ctx->err = "PCG reached maxit";
+  return STS_NOT_CONVERGED;
+}
+
+sts_status sts_be_residual(sts_ctx *ctx, const double *u_n, const double *x, double dt,
+                           double *relres) {
+  if (!ctx || !relres) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (!u_n || !x) FAIL(STS_EINVAL, "null array");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "dt must be finite, > 0");
+  double *fac;
+  const int one[3] = {1, 1, 1};
+  sts_status st = pcg_workspace(ctx, STS_PC_JACOBI, one, &fac);
+  if (st) return st;
+  const long long n = ctx->ncell, cap = ctx->red_cap;
+  double *b = ctx->d_pcg, *invd = b + n;
+  launch_be_rhs(ctx, u_n, dt, b, invd, ctx->d_red + 2 * cap);
+  launch_true_residual(ctx, b, x, dt, ctx->d_red);
+  launch_sum2(ctx, ctx->d_red, stencil_parts(ctx), ctx->d_tmp);
+  LAUNCHCHK();
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, ctx->d_tmp, 16, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *relres = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  return STS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations shared by the host API and the kernel translation
+// units of libsts.  Device kernels are launched only through the host
+// launchers declared here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/sts.h"
+
+namespace sts {
+
+// ---------------------------------------------------------------------------
+// Separable geometry.  Every geometric factor of the finite-volume operator
+// is a product of 1D tables along the three axes (spherical or Cartesian):
+//   V      = V0[i] V1[j] V2[k]
+//   A_a    = Aa0[i] Aa1[j] Aa2[k]            (area of the +a face of a cell)
+//   1/dl_0 = IL00[i]                         (centre distance across +r face)
+//   1/dl_1 = IL10[i] IL11[j]
+//   1/dl_2 = IL20[i] IL21[j] IL22[k]
+// IL00 / IL11 / IL22 hold 0 where the +face does not exist (last cell of a
+// non-periodic axis).  Dirichlet faces on axis 0: area AB[s] A01[j] A02[k],
+// centre-to-face distance DB[s].
+// ---------------------------------------------------------------------------
+enum Tab0 { T_V0, T_A00, T_A10, T_A20, T_IL00, T_IL10, T_IL20, NT0 };
+enum Tab1 { T_V1, T_A01, T_A11, T_A21, T_IL11, T_IL21, NT1 };
+enum Tab2 { T_V2, T_A02, T_A12, T_A22, T_IL22, NT2 };
+
+struct Grid {
+  int n0, n1, n2;
+  int per0, per1, per2;      // periodic flags
+  int dir_lo, dir_hi;        // Dirichlet on axis-0 low / high side
+  const double *t0, *t1, *t2;  // tables: t0[tab * n0 + i] etc.
+  double ab_lo, ab_hi, db_lo, db_hi;
+};
+
+// Coefficients of the 19-point conduction operator (per-cell arrays) or of
+// the isotropic 7-point operator (nu only).
+struct Coef {
+  const double *w0, *w1, *w2;     // face weights on +a faces of each cell
+  const double *k01, *k02, *k12;  // edge weights, edge origin = the cell
+  const double *wb_lo, *wb_hi;    // Dirichlet face weights [n1*n2]
+  const double *ub_lo, *ub_hi;    // Dirichlet values [n1*n2]
+  double nu;                      // isotropic mode
+};
+
+enum OpKind { OP_NONE = 0, OP_SPITZER = 1, OP_ISOTROPIC = 2 };
+
+// PCG scalars kept on the device (alpha / beta never leave it).
+struct PcgScalars {
+  double rr;      // r . z
+  double rr_old;
+  double alpha, beta;
+  double bnorm2;  // ||b||^2
+  double rnorm2;  // ||r||^2
+  double py;
+  double tol2;    // (rtol ||b||)^2
+  int done;       // 1 once converged / broken down; later kernels no-op
+  int iters;
+  int status;     // 0 ok, 1 converged, -4 breakdown
+  int maxit;
+};
+
+}  // namespace sts
+
+struct sts_ctx {
+  int coord = 0;
+  int n0 = 0, n1 = 0, n2 = 0;
+  long long ncell = 0;
+  int bc[6] = {0, 0, 0, 0, 0, 0};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // geometry tables
+  double *d_t0 = nullptr, *d_t1 = nullptr, *d_t2 = nullptr;
+  double ab_lo = 0, ab_hi = 0, db_lo = 0, db_hi = 0;
+
+  // operator
+  int op = sts::OP_NONE;
+  double nu = 0.0;
+  double *d_w = nullptr;      // 6 * ncell: w0 w1 w2 k01 k02 k12
+  double *d_sdiag = nullptr;  // S_cc (homogeneous diagonal) per cell
+  double *d_bnd = nullptr;    // 4 * n1*n2: wb_lo wb_hi ub_lo ub_hi
+  double ub_const[2] = {0.0, 0.0};
+  bool ub_array[2] = {false, false};
+  double dt_euler = -1.0;     // cached Gershgorin limit (< 0: not computed)
+
+  // workspace
+  double *d_rk = nullptr;     // RKL2: F0, Ya, Yb (3 * ncell * ncomp_cap)
+  int rk_ncomp = 0;
+  double *d_pcg = nullptr;    // PCG vectors
+  double *d_red = nullptr;    // reduction partials
+  int red_cap = 0;
+  sts::PcgScalars *d_sc = nullptr;
+  sts::PcgScalars *h_sc = nullptr;  // pinned mirror
+  double *d_ilu = nullptr;    // block ILU0 factors
+  long long ilu_cap = 0;
+  int *d_flag = nullptr;      // device flags (input checks, ILU breakdown)
+  double *d_tmp = nullptr;    // small device scratch for host-read scalars
+  void *h_pin = nullptr;      // pinned host mirror of flags / scalars
+
+  sts::Grid grid() const;
+  sts::Coef coef() const;
+};
+
+namespace sts {
+
+// geometry / coefficient setup (k_coef.hip)
+void launch_spitzer_coef(const sts_ctx *c, const double *T, double kappa0, const double *b0,
+                         const double *b1, const double *b2);
+void launch_dirichlet_weights(const sts_ctx *c);
+void launch_sdiag(const sts_ctx *c);
+void launch_gershgorin(const sts_ctx *c, double *partials, int nparts);
+int gershgorin_parts(const sts_ctx *c);
+
+// stencil kernels (k_stencil.hip)
+// mode 0: out = F(u); mode 1: F0 = F(u0), out = u0 + mut_dt F0;
+// mode 2: out = mu ukm1 + nu ukm2 + (1-mu-nu) u0 + mut_dt F(ukm1) + gt_dt F0
+void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, const double *ukm2,
+                  const double *u0, double *F0, double *out, double mu, double nu, double mut_dt,
+                  double gt_dt);
+
+// PCG (k_pcg.hip).  Partial-sum buffers hold two regions of red_cap values.
+int stencil_parts(const sts_ctx *c);  // workgroups of the 3D-tiled kernels
+int pass_b_parts(const sts_ctx *c);   // workgroups of the 1D kernels
+int pcg_parts(const sts_ctx *c);      // max of the two
+void launch_be_rhs(const sts_ctx *c, const double *u_n, double dt, double *b, double *invd,
+                   double *part);
+void launch_residual_init(const sts_ctx *c, const double *b, const double *x, double dt,
+                          const double *invd, const double *zilu, double *r, double *p,
+                          double *part);
+void launch_init_p(const sts_ctx *c, const double *r, const double *invd, const double *zilu,
+                   double *p, double *part);
+void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr,
+                           const double *prz, PcgScalars *sc, double rtol, int maxit);
+void launch_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
+                   const double *zilu, const double *pold, double *pnew, double *y, double *part,
+                   const PcgScalars *sc, int first);
+void launch_finalize_alpha(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
+void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
+                          const double *y, const double *invd, double *part,
+                          const PcgScalars *sc);
+void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
+void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,
+                          double *part);
+void launch_sum2(const sts_ctx *c, const double *part, int nparts, double *out2);
+void launch_fill(const sts_ctx *c, double *p, long long n, double v);
+void launch_check_spitzer(const sts_ctx *c, const double *T, const double *b0, const double *b1,
+                          const double *b2, int *flag);
+
+// block ILU0 (k_ilu.hip)
+int ilu_nblocks(const sts_ctx *c, const int block[3]);
+void launch_ilu_factor(const sts_ctx *c, double dt, const int block[3], double *fac, int *bad);
+void launch_ilu_apply_init(const sts_ctx *c, const int block[3], const double *fac,
+                           const double *r, double *z);
+void launch_pass_b_ilu(const sts_ctx *c, const int block[3], const double *fac, double *x,
+                       const double *p, double *r, const double *y, double *z, double *part,
+                       const PcgScalars *sc);
+int ilu_parts(const sts_ctx *c, const int block[3]);
+
+}  // namespace sts

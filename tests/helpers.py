@@ -1,0 +1,78 @@
+"""Shared test plumbing: build the same seeded inputs for the oracle and for
+the HIP library, and compare results."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import operator as O
+from workloads import make_workload, shell_faces, temperature, dipole_bhat
+
+ORACLE_BC = {0: O.ZEROFLUX, 1: O.DIRICHLET, 2: O.PERIODIC}
+
+
+def oracle_spitzer(rf, thf, phf, T, br, bt, bp, kappa0, bc, u_lo=0.0, u_hi=0.0,
+                   coord="spherical"):
+    D = O.spitzer_tensor(T, kappa0, br, bt, bp)
+    obc = tuple(ORACLE_BC[b] for b in bc)
+    return O.assemble(coord, rf, thf, phf, D, obc, u_lo=u_lo, u_hi=u_hi)
+
+
+def gpu_spitzer(sts, rf, thf, phf, T, br, bt, bp, kappa0, bc, u_lo=0.0, u_hi=0.0,
+                coord=None):
+    import torch
+    coord = sts.SPHERICAL if coord is None else coord
+    ctx = sts.Context(coord, rf, thf, phf, bc)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    if bc[0] == sts.BC_DIRICHLET:
+        ctx.set_dirichlet(0, value=u_lo)
+    if bc[1] == sts.BC_DIRICHLET:
+        ctx.set_dirichlet(1, value=u_hi)
+    ctx.set_spitzer(dev(T), kappa0, dev(br), dev(bt), dev(bp))
+    return ctx
+
+
+def small_shell(shape, seed=1):
+    rf, thf, phf = shell_faces(*shape)
+    T = temperature(rf, thf, phf, seed)
+    br, bt, bp = dipole_bhat(rf, thf, phf)
+    return dict(rf=rf, thf=thf, phf=phf, T=T, br=br, bt=bt, bp=bp, kappa0=1e-15,
+                T_inner=1.5e6)
+
+
+def relmax(a, b, scale=None):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    s = np.max(np.abs(b)) if scale is None else scale
+    return float(np.max(np.abs(a - b)) / (s if s > 0 else 1.0))
+
+
+def window_F(w, cells, half=2):
+    """F(T) at the given cells, each computed by the oracle on a small window
+    of the grid around the cell (exact: a row of F only involves cells within
+    one cell, whose coefficients involve cells within two)."""
+    rf, thf, phf = w["rf"], w["thf"], w["phf"]
+    n0, n1, n2 = len(rf) - 1, len(thf) - 1, len(phf) - 1
+    out = []
+    for (i, j, k) in cells:
+        i0, i1 = max(0, i - half), min(n0, i + half + 1)
+        j0, j1 = max(0, j - half), min(n1, j + half + 1)
+        ks = [(k + d) % n2 for d in range(-half, half + 1)]
+        # unwrap phi faces of the window
+        pf = [phf[ks[0]]]
+        for kk in ks:
+            pf.append(pf[-1] + (phf[kk + 1] - phf[kk]))
+        pf = np.array(pf)
+        sl = (slice(i0, i1), slice(j0, j1))
+        take = lambda a: a[sl][:, :, ks]  # noqa: E731
+        bc = [O.DIRICHLET if i0 == 0 else O.ZEROFLUX, O.ZEROFLUX, O.ZEROFLUX, O.ZEROFLUX,
+              O.ZEROFLUX, O.ZEROFLUX]
+        D = O.spitzer_tensor(take(w["T"]), w["kappa0"], take(w["br"]), take(w["bt"]),
+                             take(w["bp"]))
+        op = O.assemble("spherical", rf[i0:i1 + 1], thf[j0:j1 + 1], pf, D, tuple(bc),
+                        u_lo=w["T_inner"])
+        F = O.apply_F(op, take(w["T"]))
+        out.append(F[i - i0, j - j0, half])
+    return np.array(out)
+
+
+__all__ = ["oracle_spitzer", "gpu_spitzer", "small_shell", "relmax", "window_F", "make_workload"]

@@ -104,7 +104,7 @@ def dipole_bhat(rf, thf, phf, tilt_deg: float = 30.0):
     nrm = np.sqrt(br * br + bt * bt + bp * bp)
     nr = len(rf) - 1
     shape = (nr,) + br.shape
-    return tuple(np.ascontiguousarray(np.broadcast_to(c / nrm, shape)) for c in (br, bt, bp))
+    return tuple(np.broadcast_to(c / nrm, shape).copy() for c in (br, bt, bp))
 
 
 def random_unit_vectors(shape, seed: int):

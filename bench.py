@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", default="rkl2,jacobi,ilu0",
                     help="comma list of timed phases (profiling runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="before the steps, run a plain device copy of 4 fields (known bytes) "
+                         "that calibrates the HBM byte counters")
     return ap.parse_args()
 
 
@@ -81,6 +84,14 @@ def main():
     ncell = T.numel()
     phases = args.phases.split(",")
     stream = torch.cuda.current_stream()
+
+    if args.copy_calib:
+        src = torch.empty(4 * ncell, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(rec):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]

@@ -116,112 +116,6 @@ __device__ __forceinline__ double edge_term(double K, double u00, double u10, do
   return 0.5 * K * ((p ? -ya : ya) + (q ? -xb : xb));
 }
 
-// A source of stencil values: plain array read.
-struct ArrayField {
-  const double *__restrict__ u;
-  __device__ __forceinline__ double operator()(int idx) const { return u[idx]; }
-};
-
-// (S u)_c (+ g_c when WITH_G) for the 19-point conduction operator.
-template <bool WITH_G, class Field>
-__device__ __forceinline__ double s19(const Grid &g, const Coef &C, const Field &u, int i, int j,
-                                      int k) {
-  const Nb A = nbr(i, g.n0, g.per0), B = nbr(j, g.n1, g.per1), Cn = nbr(k, g.n2, g.per2);
-  const int c = lin(g, i, j, k);
-  const double u000 = u(c);
-  const double um00 = u(lin(g, A.m, j, k)), up00 = u(lin(g, A.p, j, k));
-  const double u0m0 = u(lin(g, i, B.m, k)), u0p0 = u(lin(g, i, B.p, k));
-  const double u00m = u(lin(g, i, j, Cn.m)), u00p = u(lin(g, i, j, Cn.p));
-  const double umm0 = u(lin(g, A.m, B.m, k)), ump0 = u(lin(g, A.m, B.p, k));
-  const double upm0 = u(lin(g, A.p, B.m, k)), upp0 = u(lin(g, A.p, B.p, k));
-  const double um0m = u(lin(g, A.m, j, Cn.m)), um0p = u(lin(g, A.m, j, Cn.p));
-  const double up0m = u(lin(g, A.p, j, Cn.m)), up0p = u(lin(g, A.p, j, Cn.p));
-  const double u0mm = u(lin(g, i, B.m, Cn.m)), u0mp = u(lin(g, i, B.m, Cn.p));
-  const double u0pm = u(lin(g, i, B.p, Cn.m)), u0pp = u(lin(g, i, B.p, Cn.p));
-
-  double acc = 0.0;
-  // faces (weights are zero on faces that do not exist on the + side)
-  acc += C.w0[c] * (up00 - u000);
-  if (A.hm) acc += C.w0[lin(g, A.m, j, k)] * (um00 - u000);
-  acc += C.w1[c] * (u0p0 - u000);
-  if (B.hm) acc += C.w1[lin(g, i, B.m, k)] * (u0m0 - u000);
-  acc += C.w2[c] * (u00p - u000);
-  if (Cn.hm) acc += C.w2[lin(g, i, j, Cn.m)] * (u00m - u000);
-
-  // edges, plane (0, 1)
-  {
-    EdgeGeo e;
-    e = edge_geo<0>(g, i, j, k, A, B, Cn, 0, 0);
-    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, u000, up00, u0p0, upp0, e, 0, 0);
-    e = edge_geo<0>(g, i, j, k, A, B, Cn, 1, 0);
-    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, um00, u000, ump0, u0p0, e, 1, 0);
-    e = edge_geo<0>(g, i, j, k, A, B, Cn, 0, 1);
-    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, u0m0, upm0, u000, up00, e, 0, 1);
-    e = edge_geo<0>(g, i, j, k, A, B, Cn, 1, 1);
-    acc += edge_term(e.ex ? C.k01[e.e00] : 0.0, umm0, u0m0, um00, u000, e, 1, 1);
-  }
-  // plane (0, 2)
-  {
-    EdgeGeo e;
-    e = edge_geo<1>(g, i, j, k, A, B, Cn, 0, 0);
-    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, u000, up00, u00p, up0p, e, 0, 0);
-    e = edge_geo<1>(g, i, j, k, A, B, Cn, 1, 0);
-    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, um00, u000, um0p, u00p, e, 1, 0);
-    e = edge_geo<1>(g, i, j, k, A, B, Cn, 0, 1);
-    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, u00m, up0m, u000, up00, e, 0, 1);
-    e = edge_geo<1>(g, i, j, k, A, B, Cn, 1, 1);
-    acc += edge_term(e.ex ? C.k02[e.e00] : 0.0, um0m, u00m, um00, u000, e, 1, 1);
-  }
-  // plane (1, 2)
-  {
-    EdgeGeo e;
-    e = edge_geo<2>(g, i, j, k, A, B, Cn, 0, 0);
-    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u000, u0p0, u00p, u0pp, e, 0, 0);
-    e = edge_geo<2>(g, i, j, k, A, B, Cn, 1, 0);
-    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u0m0, u000, u0mp, u00p, e, 1, 0);
-    e = edge_geo<2>(g, i, j, k, A, B, Cn, 0, 1);
-    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u00m, u0pm, u000, u0p0, e, 0, 1);
-    e = edge_geo<2>(g, i, j, k, A, B, Cn, 1, 1);
-    acc += edge_term(e.ex ? C.k12[e.e00] : 0.0, u0mm, u00m, u0m0, u000, e, 1, 1);
-  }
-  // Dirichlet faces on axis 0
-  if (g.dir_lo && i == 0) {
-    const int b = j * g.n2 + k;
-    acc += WITH_G ? C.wb_lo[b] * (C.ub_lo[b] - u000) : -C.wb_lo[b] * u000;
-  }
-  if (g.dir_hi && i == g.n0 - 1) {
-    const int b = j * g.n2 + k;
-    acc += WITH_G ? C.wb_hi[b] * (C.ub_hi[b] - u000) : -C.wb_hi[b] * u000;
-  }
-  return acc;
-}
-
-// (S u)_c (+ g_c) for the isotropic 7-point operator nu * Laplacian.
-template <bool WITH_G, class Field>
-__device__ __forceinline__ double s7(const Grid &g, const Coef &C, const Field &u, int i, int j,
-                                     int k) {
-  const Nb A = nbr(i, g.n0, g.per0), B = nbr(j, g.n1, g.per1), Cn = nbr(k, g.n2, g.per2);
-  const int c = lin(g, i, j, k);
-  const double u000 = u(c);
-  double acc = 0.0;
-  acc += area0(g, i, j, k) * il0(g, i) * (u(lin(g, A.p, j, k)) - u000);
-  if (A.hm) acc += area0(g, A.m, j, k) * il0(g, A.m) * (u(lin(g, A.m, j, k)) - u000);
-  acc += area1(g, i, j, k) * il1(g, i, j) * (u(lin(g, i, B.p, k)) - u000);
-  if (B.hm) acc += area1(g, i, B.m, k) * il1(g, i, B.m) * (u(lin(g, i, B.m, k)) - u000);
-  acc += area2(g, i, j, k) * il2(g, i, j, k) * (u(lin(g, i, j, Cn.p)) - u000);
-  if (Cn.hm) acc += area2(g, i, j, Cn.m) * il2(g, i, j, Cn.m) * (u(lin(g, i, j, Cn.m)) - u000);
-  acc *= C.nu;
-  if (g.dir_lo && i == 0) {
-    const int b = j * g.n2 + k;
-    acc += WITH_G ? C.wb_lo[b] * (C.ub_lo[b] - u000) : -C.wb_lo[b] * u000;
-  }
-  if (g.dir_hi && i == g.n0 - 1) {
-    const int b = j * g.n2 + k;
-    acc += WITH_G ? C.wb_hi[b] * (C.ub_hi[b] - u000) : -C.wb_hi[b] * u000;
-  }
-  return acc;
-}
-
 // Row c of S as a 3x3x3 array row[(dx+1)*9 + (dy+1)*3 + (dz+1)] = S[c, c+d]
 // (only the 19 stencil entries can be non-zero).  OP: 1 conduction, 2 isotropic.
 __device__ __forceinline__ void add_edge_row(double *row, int sa, int sb, double K,

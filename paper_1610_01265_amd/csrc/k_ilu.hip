@@ -18,8 +18,8 @@
 // the column (i', j') = (t / 8, t % 8), which holds at most one cell of any
 // hyperplane.
 //
-// Factor layout: fac[block][slot][B0*B1*B2] with slots 0..8 = L, 9 = D, the
-// cell index inside a block being (i' B1 + j') B2 + k'.
+// Factor layout: fac[block][slot][B0*B1*B2] with slots 0..8 = L, 9 = 1/D,
+// the cell index inside a block being (i' B1 + j') B2 + k'.
 #include "k_common.h"
 #include "k_reduce.h"
 
@@ -80,72 +80,101 @@ struct BlockGeo {
 
 constexpr int MAXB = 512;
 
+__device__ __forceinline__ bool in_block(int m0, int m1, int m2, int e0, int e1, int e2) {
+  return m0 >= 0 && m0 < e0 && m1 >= 0 && m1 < e1 && m2 >= 0 && m2 < e2;
+}
+
+// Factorisation.  Phase 1: every lane assembles the block-restricted rows of
+// A = V - dt S for 8 cells (fully parallel) into LDS.  Phase 2: hyperplane
+// by hyperplane, each lane turns its cell's row into L (in place) and the
+// pivot D.  Phase 3: L and 1/D go to HBM.
+constexpr int FTH = 256;
 template <int OP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(FTH)
     k_ilu_factor(Grid g, Coef C, double dt, BlockGeo bg, double *__restrict__ fac, int *bad) {
   __shared__ double sL[9][MAXB];
   __shared__ double sD[MAXB];
   const int bid = blockIdx.x, t = threadIdx.x;
   int o0, o1, o2, e0, e1, e2;
   bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
-  const int BS = bg.B0 * bg.B1 * bg.B2;
-  const int li = t >> 3, lj = t & 7;
-  const bool col = li < e0 && lj < e1;
-  const int nlev = 3 * (e0 - 1) + 2 * (e1 - 1) + (e2 - 1) + 1;
-  double *fb = fac + (size_t)bid * 10 * BS;
-  for (int lev = 0; lev < nlev; ++lev) {
-    const int lk = lev - 3 * li - 2 * lj;
-    if (col && lk >= 0 && lk < e2) {
+  const int B1 = bg.B1, B2 = bg.B2, BS = bg.B0 * B1 * B2;
+  for (int l = t; l < BS; l += FTH) {
+    const int li = l / (B1 * B2), rem = l - li * B1 * B2, lj = rem / B2, lk = rem - lj * B2;
+    if (li < e0 && lj < e1 && lk < e2) {
       const int gi = o0 + li, gj = o1 + lj, gk = o2 + lk;
       double row[27];
       row27<OP>(g, C, gi, gj, gk, row);
-      const int l = (li * bg.B1 + lj) * bg.B2 + lk;
-      double Lr[9];
+#pragma unroll
+      for (int s = 0; s < 9; ++s) {
+        const bool v = in_block(li + c_off[s][0], lj + c_off[s][1], lk + c_off[s][2], e0, e1, e2);
+        sL[s][l] = v ? -dt * row[13 + c_off[s][0] * 9 + c_off[s][1] * 3 + c_off[s][2]] : 0.0;
+      }
+      sD[l] = vol(g, gi, gj, gk) - dt * row[13];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 9; ++s) sL[s][l] = 0.0;
+      sD[l] = 1.0;
+    }
+  }
+  __syncthreads();
+  const int li = t >> 3, lj = t & 7;
+  const bool col = t < 64 && li < e0 && lj < e1;
+  const int nlev = 3 * (e0 - 1) + 2 * (e1 - 1) + (e2 - 1) + 1;
+  for (int lev = 0; lev < nlev; ++lev) {
+    const int lk = lev - 3 * li - 2 * lj;
+    if (col && lk >= 0 && lk < e2) {
+      const int l = (li * B1 + lj) * B2 + lk;
       int nbl[9];
       unsigned valid = 0;
 #pragma unroll
       for (int s = 0; s < 9; ++s) {
         const int m0 = li + c_off[s][0], m1 = lj + c_off[s][1], m2 = lk + c_off[s][2];
-        nbl[s] = (m0 * bg.B1 + m1) * bg.B2 + m2;
-        if (m0 >= 0 && m1 >= 0 && m1 < e1 && m2 >= 0 && m2 < e2) valid |= 1u << s;
+        nbl[s] = (m0 * B1 + m1) * B2 + m2;
+        if (in_block(m0, m1, m2, e0, e1, e2)) valid |= 1u << s;
       }
-      double dii = vol(g, gi, gj, gk) - dt * row[13];
+      double dii = sD[l];
 #pragma unroll
       for (int s = 0; s < 9; ++s) {
-        Lr[s] = 0.0;
         if (valid & (1u << s)) {
-          double a = -dt * row[13 + c_off[s][0] * 9 + c_off[s][1] * 3 + c_off[s][2]];
           const int kk = nbl[s];
+          double a = sL[s][l];
           for (int q = 0; q < c_pairs.n[s]; ++q) {
             const int sm = c_pairs.sm[s][q];
-            if (valid & (1u << sm)) a -= Lr[sm] * (sD[nbl[sm]] * sL[c_pairs.skm[s][q]][kk]);
+            if (valid & (1u << sm)) a -= sL[sm][l] * (sD[nbl[sm]] * sL[c_pairs.skm[s][q]][kk]);
           }
-          Lr[s] = a / sD[kk];
-          dii -= Lr[s] * (sD[kk] * Lr[s]);
+          const double Lv = a / sD[kk];
+          sL[s][l] = Lv;
+          dii -= Lv * (sD[kk] * Lv);
         }
       }
-#pragma unroll
-      for (int s = 0; s < 9; ++s) {
-        sL[s][l] = Lr[s];
-        fb[s * BS + l] = Lr[s];
-      }
       sD[l] = dii;
-      fb[9 * BS + l] = dii;
       if (!(dii > 0.0)) atomicOr(bad, 1);
     }
     __syncthreads();
   }
+  double *fb = fac + (size_t)bid * 10 * BS;
+  for (int l = t; l < BS; l += FTH) {
+#pragma unroll
+    for (int s = 0; s < 9; ++s) fb[s * BS + l] = sL[s][l];
+    fb[9 * BS + l] = 1.0 / sD[l];
+  }
 }
 
 // z = (L D L^T)^-1 r on each block.  UPDATE: first x += alpha p, r -= alpha y
-// (the PCG pass-B axpys), and reduce r.z and r.r.
+// (the PCG pass-B axpys), and reduce r.z and r.r.  The block's factors are
+// staged in LDS once by all four wavefronts (coalesced, loads issued
+// unconditionally with clamped indices); wavefront 0 then runs both
+// substitution sweeps out of LDS, while the others wait at the barriers.
+constexpr int ATH = 256;
 template <bool UPDATE>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(ATH)
     k_ilu_apply(Grid g, BlockGeo bg, const double *__restrict__ fac, double *__restrict__ x,
                 const double *__restrict__ p, double *__restrict__ r,
                 const double *__restrict__ y, double *__restrict__ z, double *part,
                 long long cap, const PcgScalars *sc) {
   if (UPDATE && sc->done) return;
+  __shared__ double sL[9][MAXB];
+  __shared__ double sI[MAXB];  // 1 / D
   __shared__ double sz[MAXB];
   __shared__ double sr[MAXB];
   const int bid = blockIdx.x, t = threadIdx.x;
@@ -154,38 +183,73 @@ __global__ void __launch_bounds__(64)
   const int B1 = bg.B1, B2 = bg.B2, BS = bg.B0 * B1 * B2;
   const double *fb = fac + (size_t)bid * 10 * BS;
   const double alpha = UPDATE ? sc->alpha : 0.0;
-  for (int l = t; l < BS; l += 64) {
+  constexpr int PER = MAXB / ATH;  // cells per thread in the load / store phases
+  // factors -> LDS
+#pragma unroll
+  for (int s = 0; s < 10; ++s) {
+    double v[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) v[m] = fb[s * BS + min(t + ATH * m, BS - 1)];
+#pragma unroll
+    for (int m = 0; m < PER; ++m)
+      if (t + ATH * m < BS) (s < 9 ? sL[s] : sI)[t + ATH * m] = v[m];
+  }
+  // x, r updates; r -> LDS
+  int cidx[PER];
+  bool cval[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int l = t + ATH * m;
     const int li = l / (B1 * B2), rem = l - li * B1 * B2, lj = rem / B2, lk = rem - lj * B2;
-    double rv = 0.0;
-    if (li < e0 && lj < e1 && lk < e2) {
-      const int c = lin(g, o0 + li, o1 + lj, o2 + lk);
-      if (UPDATE) {
-        x[c] = x[c] + alpha * p[c];
-        rv = r[c] - alpha * y[c];
-        r[c] = rv;
-      } else {
-        rv = r[c];
+    cval[m] = l < BS && li < e0 && lj < e1 && lk < e2;
+    cidx[m] = lin(g, o0 + min(li, e0 - 1), o1 + min(lj, e1 - 1), o2 + min(lk, e2 - 1));
+  }
+  double rl[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int c = cidx[m];
+    if (UPDATE) {
+      const double xv = x[c], pv = p[c], rv = r[c], yv = y[c];
+      rl[m] = cval[m] ? rv - alpha * yv : 0.0;
+      if (cval[m]) {
+        x[c] = xv + alpha * pv;
+        r[c] = rl[m];
       }
+    } else {
+      const double rv = r[c];
+      rl[m] = cval[m] ? rv : 0.0;
     }
-    sr[l] = rv;
-    sz[l] = rv;
+    const int l = t + ATH * m;
+    if (l < BS) {
+      sz[l] = rl[m];
+      sr[l] = rl[m];
+    }
   }
   __syncthreads();
   const int li = t >> 3, lj = t & 7;
-  const bool col = li < e0 && lj < e1;
+  const bool col = t < 64 && li < e0 && lj < e1;
   const int nlev = 3 * (e0 - 1) + 2 * (e1 - 1) + (e2 - 1) + 1;
+  // Both sweeps are branch-free: L entries of neighbours outside the block
+  // are stored as zero, so a neighbour index only has to stay inside the
+  // LDS arrays (clamped); the 18 LDS reads of a row can then all be issued
+  // before the multiply-add chain.
+  int loff[9];
+#pragma unroll
+  for (int s = 0; s < 9; ++s) loff[s] = (c_off[s][0] * B1 + c_off[s][1]) * B2 + c_off[s][2];
   // forward: z*_i = r_i - sum_k L_ik z*_k
   for (int lev = 0; lev < nlev; ++lev) {
     const int lk = lev - 3 * li - 2 * lj;
     if (col && lk >= 0 && lk < e2) {
       const int l = (li * B1 + lj) * B2 + lk;
-      double acc = sz[l];
+      double lv[9], zv[9];
 #pragma unroll
       for (int s = 0; s < 9; ++s) {
-        const int m0 = li + c_off[s][0], m1 = lj + c_off[s][1], m2 = lk + c_off[s][2];
-        if (m0 >= 0 && m1 >= 0 && m1 < e1 && m2 >= 0 && m2 < e2)
-          acc -= fb[s * BS + l] * sz[(m0 * B1 + m1) * B2 + m2];
+        lv[s] = sL[s][l];
+        zv[s] = sz[min(max(l + loff[s], 0), BS - 1)];
       }
+      double acc = sz[l];
+#pragma unroll
+      for (int s = 0; s < 9; ++s) acc -= lv[s] * zv[s];
       sz[l] = acc;
     }
     __syncthreads();
@@ -195,38 +259,32 @@ __global__ void __launch_bounds__(64)
     const int lk = lev - 3 * li - 2 * lj;
     if (col && lk >= 0 && lk < e2) {
       const int l = (li * B1 + lj) * B2 + lk;
-      double acc = sz[l] / fb[9 * BS + l];
+      double lv[9], zv[9];
 #pragma unroll
       for (int s = 0; s < 9; ++s) {
-        const int m0 = li - c_off[s][0], m1 = lj - c_off[s][1], m2 = lk - c_off[s][2];
-        if (m0 < e0 && m1 >= 0 && m1 < e1 && m2 >= 0 && m2 < e2) {
-          const int j = (m0 * B1 + m1) * B2 + m2;
-          acc -= fb[s * BS + j] * sz[j];
-        }
+        const int j = min(max(l - loff[s], 0), BS - 1);
+        lv[s] = (l - loff[s] == j) ? sL[s][j] : 0.0;
+        zv[s] = sz[j];
       }
+      double acc = sz[l] * sI[l];
+#pragma unroll
+      for (int s = 0; s < 9; ++s) acc -= lv[s] * zv[s];
       sz[l] = acc;
     }
     __syncthreads();
   }
   double rz = 0.0, rr = 0.0;
-  for (int l = t; l < BS; l += 64) {
-    const int li2 = l / (B1 * B2), rem = l - li2 * B1 * B2, lj2 = rem / B2, lk2 = rem - lj2 * B2;
-    if (li2 < e0 && lj2 < e1 && lk2 < e2) {
-      const int c = lin(g, o0 + li2, o1 + lj2, o2 + lk2);
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int l = t + ATH * m;
+    if (cval[m]) {
       const double zv = sz[l];
-      z[c] = zv;
+      z[cidx[m]] = zv;
       rz += sr[l] * zv;
       rr += sr[l] * sr[l];
     }
   }
-  if (part) {
-    rz = wave_sum(rz);
-    rr = wave_sum(rr);
-    if (t == 0) {
-      part[bid] = rz;
-      part[cap + bid] = rr;
-    }
-  }
+  if (part) wg_sum2<ATH>(rz, rr, t, part + bid, part + cap + bid);
 }
 
 BlockGeo block_geo(const sts_ctx *c, const int block[3]) {
@@ -251,17 +309,17 @@ int ilu_parts(const sts_ctx *c, const int block[3]) { return ilu_nblocks(c, bloc
 void launch_ilu_factor(const sts_ctx *c, double dt, const int block[3], double *fac, int *bad) {
   const int nb = ilu_nblocks(c, block);
   if (c->op == OP_SPITZER)
-    hipLaunchKernelGGL(k_ilu_factor<OP_SPITZER>, dim3(nb), dim3(64), 0, c->stream, c->grid(),
+    hipLaunchKernelGGL(k_ilu_factor<OP_SPITZER>, dim3(nb), dim3(FTH), 0, c->stream, c->grid(),
                        c->coef(), dt, block_geo(c, block), fac, bad);
   else
-    hipLaunchKernelGGL(k_ilu_factor<OP_ISOTROPIC>, dim3(nb), dim3(64), 0, c->stream, c->grid(),
+    hipLaunchKernelGGL(k_ilu_factor<OP_ISOTROPIC>, dim3(nb), dim3(FTH), 0, c->stream, c->grid(),
                        c->coef(), dt, block_geo(c, block), fac, bad);
 }
 
 void launch_ilu_apply_init(const sts_ctx *c, const int block[3], const double *fac,
                            const double *r, double *z) {
   const int nb = ilu_nblocks(c, block);
-  hipLaunchKernelGGL(k_ilu_apply<false>, dim3(nb), dim3(64), 0, c->stream, c->grid(),
+  hipLaunchKernelGGL(k_ilu_apply<false>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
                      block_geo(c, block), fac, (double *)nullptr, (const double *)nullptr,
                      const_cast<double *>(r), (const double *)nullptr, z, (double *)nullptr, 0LL,
                      (const PcgScalars *)nullptr);
@@ -271,7 +329,7 @@ void launch_pass_b_ilu(const sts_ctx *c, const int block[3], const double *fac, 
                        const double *p, double *r, const double *y, double *z, double *part,
                        const PcgScalars *sc) {
   const int nb = ilu_nblocks(c, block);
-  hipLaunchKernelGGL(k_ilu_apply<true>, dim3(nb), dim3(64), 0, c->stream, c->grid(),
+  hipLaunchKernelGGL(k_ilu_apply<true>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
                      block_geo(c, block), fac, x, p, r, y, z, part, (long long)c->red_cap, sc);
 }
 

@@ -21,10 +21,6 @@ namespace {
 
 constexpr int TX = 64, TY = 4, NT = TX * TY;
 
-__device__ __forceinline__ int wg_id3() {
-  return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-}
-
 __device__ __forceinline__ double g_term(const Grid &g, const Coef &C, int i, int j, int k) {
   double t = 0.0;
   const int b = j * g.n2 + k;
@@ -37,58 +33,28 @@ template <int OP>
 __global__ void __launch_bounds__(NT)
     k_be_rhs(Grid g, Coef C, const double *__restrict__ un, double dt,
              const double *__restrict__ sdiag, double *__restrict__ b,
-             double *__restrict__ invd, double *part) {
+             double *__restrict__ invd) {
   const int k = blockIdx.x * TX + threadIdx.x;
   const int j = blockIdx.y * TY + threadIdx.y;
   const int i = blockIdx.z;
-  const int tid = threadIdx.y * TX + threadIdx.x;
-  double bb = 0.0;
   if (k < g.n2 && j < g.n1) {
     const int c = lin(g, i, j, k);
     const double V = vol(g, i, j, k);
-    const double v = V * un[c] + dt * g_term(g, C, i, j, k);
-    b[c] = v;
+    b[c] = V * un[c] + dt * g_term(g, C, i, j, k);
     invd[c] = 1.0 / (V - dt * sdiag[c]);
-    bb = v * v;
   }
-  wg_sum2<NT>(bb, 0.0, tid, part + wg_id3(), nullptr);
-}
-
-// r = b - A x; partial sums of r . r.  WRITE = false: norms only.
-template <int OP, bool WRITE>
-__global__ void __launch_bounds__(NT)
-    k_resid(Grid g, Coef C, const double *__restrict__ b, const double *__restrict__ x, double dt,
-            double *__restrict__ r, double *part, long long cap) {
-  const int k = blockIdx.x * TX + threadIdx.x;
-  const int j = blockIdx.y * TY + threadIdx.y;
-  const int i = blockIdx.z;
-  const int tid = threadIdx.y * TX + threadIdx.x;
-  double rr = 0.0, bb = 0.0;
-  if (k < g.n2 && j < g.n1) {
-    const int c = lin(g, i, j, k);
-    const ArrayField f{x};
-    const double su = (OP == OP_SPITZER) ? s19<false>(g, C, f, i, j, k)
-                                         : s7<false>(g, C, f, i, j, k);
-    const double ax = vol(g, i, j, k) * x[c] - dt * su;
-    const double rv = b[c] - ax;
-    if (WRITE) r[c] = rv;
-    rr = rv * rv;
-    bb = b[c] * b[c];
-  }
-  const int w = wg_id3();
-  wg_sum2<NT>(rr, bb, tid, part + w, part + cap + w);
 }
 
 // p = z (z = invd r for Jacobi, or the given z); partial sums r . z
 __global__ void __launch_bounds__(NT)
     k_init_p(long long n, const double *__restrict__ r, const double *__restrict__ invd,
              const double *__restrict__ zilu, double *__restrict__ p, double *part) {
-  const long long c = (long long)blockIdx.x * NT + threadIdx.x;
   double rz = 0.0;
-  if (c < n) {
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
     const double z = zilu ? zilu[c] : invd[c] * r[c];
     p[c] = z;
-    rz = r[c] * z;
+    rz += r[c] * z;
   }
   wg_sum2<NT>(rz, 0.0, threadIdx.x, part + blockIdx.x, nullptr);
 }
@@ -127,46 +93,6 @@ __global__ void k_fin_init(const double *pb, int nb, const double *prr, int nrr,
   }
 }
 
-// z at a stencil point: Jacobi (r / A_ii) or a stored block-ILU0 result.
-template <int PC>
-struct PField {
-  const double *__restrict__ r;
-  const double *__restrict__ invd;
-  const double *__restrict__ zilu;
-  const double *__restrict__ pold;
-  double beta;
-  __device__ __forceinline__ double operator()(int idx) const {
-    const double z = (PC == STS_PC_JACOBI) ? r[idx] * invd[idx] : zilu[idx];
-    return pold ? z + beta * pold[idx] : z;
-  }
-};
-
-template <int OP, int PC>
-__global__ void __launch_bounds__(NT)
-    k_pass_a(Grid g, Coef C, double dt, const double *__restrict__ r,
-             const double *__restrict__ invd, const double *__restrict__ zilu,
-             const double *__restrict__ pold, double *__restrict__ pnew,
-             double *__restrict__ y, double *part, const PcgScalars *sc, int first) {
-  if (sc->done) return;
-  const int k = blockIdx.x * TX + threadIdx.x;
-  const int j = blockIdx.y * TY + threadIdx.y;
-  const int i = blockIdx.z;
-  const int tid = threadIdx.y * TX + threadIdx.x;
-  double py = 0.0;
-  if (k < g.n2 && j < g.n1) {
-    const PField<PC> f{r, invd, zilu, first ? nullptr : pold, first ? 0.0 : sc->beta};
-    const int c = lin(g, i, j, k);
-    const double pc = f(c);
-    const double su = (OP == OP_SPITZER) ? s19<false>(g, C, f, i, j, k)
-                                         : s7<false>(g, C, f, i, j, k);
-    const double yc = vol(g, i, j, k) * pc - dt * su;
-    pnew[c] = pc;
-    y[c] = yc;
-    py = pc * yc;
-  }
-  wg_sum2<NT>(py, 0.0, tid, part + wg_id3(), nullptr);
-}
-
 __global__ void k_fin_alpha(const double *part, int n, PcgScalars *sc) {
   if (sc->done) return;
   __shared__ double s;
@@ -183,6 +109,8 @@ __global__ void k_fin_alpha(const double *part, int n, PcgScalars *sc) {
   }
 }
 
+// Grid-stride over the cells with a bounded number of workgroups, so the
+// finalize kernel sums few partials.
 __global__ void __launch_bounds__(NT)
     k_pass_b_jac(long long n, double *__restrict__ x, const double *__restrict__ p,
                  double *__restrict__ r, const double *__restrict__ y,
@@ -190,15 +118,14 @@ __global__ void __launch_bounds__(NT)
                  const PcgScalars *sc) {
   if (sc->done) return;
   const double alpha = sc->alpha;
-  const long long c = (long long)blockIdx.x * NT + threadIdx.x;
   double rz = 0.0, rr = 0.0;
-  if (c < n) {
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
     x[c] = x[c] + alpha * p[c];
     const double rn = r[c] - alpha * y[c];
     r[c] = rn;
-    const double z = rn * invd[c];
-    rz = rn * z;
-    rr = rn * rn;
+    rz += rn * (rn * invd[c]);
+    rr += rn * rn;
   }
   wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
 }
@@ -246,8 +173,7 @@ long long cap_of(const sts_ctx *c) { return c->red_cap; }
 }  // namespace
 
 int pcg_parts(const sts_ctx *c) {
-  const dim3 g = grid3(c);
-  const long long n3 = (long long)g.x * g.y * g.z;
+  const long long n3 = stencil_parts(c);
   const long long n1 = (c->ncell + NT - 1) / NT;
   return (int)(n3 > n1 ? n3 : n1);
 }
@@ -256,104 +182,50 @@ void launch_be_rhs(const sts_ctx *c, const double *u_n, double dt, double *b, do
                    double *part) {
   if (c->op == OP_SPITZER)
     hipLaunchKernelGGL(k_be_rhs<OP_SPITZER>, grid3(c), dim3(TX, TY), 0, c->stream, c->grid(),
-                       c->coef(), u_n, dt, c->d_sdiag, b, invd, part);
+                       c->coef(), u_n, dt, c->d_sdiag, b, invd);
   else
     hipLaunchKernelGGL(k_be_rhs<OP_ISOTROPIC>, grid3(c), dim3(TX, TY), 0, c->stream,
-                       c->grid(), c->coef(), u_n, dt, c->d_sdiag, b, invd, part);
-}
-
-// r = b - A x (part region 0: r.r), then p = z (part region 2: r.z) and the
-// initial scalars (b.b from region 1 of the rhs launch).
-void launch_residual_init(const sts_ctx *c, const double *b, const double *x, double dt,
-                          const double *invd, const double *zilu, double *r, double *p,
-                          double *part) {
-  const long long cap = cap_of(c);
-  if (c->op == OP_SPITZER)
-    hipLaunchKernelGGL((k_resid<OP_SPITZER, true>), grid3(c), dim3(TX, TY), 0, c->stream,
-                       c->grid(), c->coef(), b, x, dt, r, part, cap);
-  else
-    hipLaunchKernelGGL((k_resid<OP_ISOTROPIC, true>), grid3(c), dim3(TX, TY), 0, c->stream,
-                       c->grid(), c->coef(), b, x, dt, r, part, cap);
-  (void)invd;
-  (void)zilu;
-  (void)p;
+                       c->grid(), c->coef(), u_n, dt, c->d_sdiag, b, invd);
 }
 
 void launch_init_p(const sts_ctx *c, const double *r, const double *invd, const double *zilu,
                    double *p, double *part) {
   const long long n = c->ncell;
-  hipLaunchKernelGGL(k_init_p, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, c->stream, n,
+  hipLaunchKernelGGL(k_init_p, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, n,
                      r, invd, zilu, p, part);
 }
 
 void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr,
                            const double *prz, PcgScalars *sc, double rtol, int maxit) {
-  const dim3 g = grid3(c);
-  const int n3 = (int)(g.x * g.y * g.z);
-  const int n1 = (int)((c->ncell + NT - 1) / NT);
+  const int n3 = stencil_parts(c);
+  const int n1 = pass_b_parts(c);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(256), 0, c->stream, pb, n3, prr, n3, prz, n1, sc,
                      rtol, maxit);
 }
 
-void launch_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
-                   const double *zilu, const double *pold, double *pnew, double *y, double *part,
-                   const PcgScalars *sc, int first) {
-  const dim3 g = grid3(c), b(TX, TY);
-  if (c->op == OP_SPITZER) {
-    if (zilu)
-      hipLaunchKernelGGL((k_pass_a<OP_SPITZER, STS_PC_BLOCK_ILU0>), g, b, 0, c->stream,
-                         c->grid(), c->coef(), dt, r, invd, zilu, pold, pnew, y, part, sc, first);
-    else
-      hipLaunchKernelGGL((k_pass_a<OP_SPITZER, STS_PC_JACOBI>), g, b, 0, c->stream, c->grid(),
-                         c->coef(), dt, r, invd, zilu, pold, pnew, y, part, sc, first);
-  } else {
-    if (zilu)
-      hipLaunchKernelGGL((k_pass_a<OP_ISOTROPIC, STS_PC_BLOCK_ILU0>), g, b, 0, c->stream,
-                         c->grid(), c->coef(), dt, r, invd, zilu, pold, pnew, y, part, sc, first);
-    else
-      hipLaunchKernelGGL((k_pass_a<OP_ISOTROPIC, STS_PC_JACOBI>), g, b, 0, c->stream,
-                         c->grid(), c->coef(), dt, r, invd, zilu, pold, pnew, y, part, sc, first);
-  }
-}
-
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars *sc) {
-  const dim3 g = grid3(c);
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, c->stream, part,
-                     (int)(g.x * g.y * g.z), sc);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, c->stream, part, stencil_parts(c), sc);
 }
 
 void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
                           const double *y, const double *invd, double *part,
                           const PcgScalars *sc) {
-  const long long n = c->ncell;
-  hipLaunchKernelGGL(k_pass_b_jac, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, c->stream,
-                     n, x, p, r, y, invd, part, cap_of(c), sc);
+  hipLaunchKernelGGL(k_pass_b_jac, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, x, p,
+                     r, y, invd, part, cap_of(c), sc);
 }
 
 void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc) {
   hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, c->stream, part, nparts, cap_of(c), sc);
 }
 
-int pass_b_parts(const sts_ctx *c) { return (int)((c->ncell + NT - 1) / NT); }
-
-void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,
-                          double *part) {
-  const long long cap = cap_of(c);
-  if (c->op == OP_SPITZER)
-    hipLaunchKernelGGL((k_resid<OP_SPITZER, false>), grid3(c), dim3(TX, TY), 0, c->stream,
-                       c->grid(), c->coef(), b, x, dt, (double *)nullptr, part, cap);
-  else
-    hipLaunchKernelGGL((k_resid<OP_ISOTROPIC, false>), grid3(c), dim3(TX, TY), 0, c->stream,
-                       c->grid(), c->coef(), b, x, dt, (double *)nullptr, part, cap);
+int pass_b_parts(const sts_ctx *c) {
+  const long long n = (c->ncell + NT - 1) / NT;
+  return (int)(n < 2048 ? n : 2048);
 }
 
 void launch_sum2(const sts_ctx *c, const double *part, int nparts, double *out2) {
   hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, c->stream, part, nparts, cap_of(c), out2);
 }
 
-int stencil_parts(const sts_ctx *c) {
-  const dim3 g = grid3(c);
-  return (int)(g.x * g.y * g.z);
-}
 
 }  // namespace sts

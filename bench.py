@@ -4,7 +4,8 @@ One step = one pass of the whole path over the synthetic shell input:
   coefficient setup (lagged Spitzer diffusivity, face / edge weights,
   Gershgorin dt_Euler), one RKL2 super-step at dt = f dt_Euler, one BE step
   solved by Jacobi-PCG and one by block-ILU0(8^3)-PCG, each to the workload's
-  relative residual.
+  relative residual; then the FP32 precision form of the RKL2 step and of the
+  Jacobi-PCG solve (mixed-precision refinement to the same FP64 residual).
 Inputs are resident in HBM before the timed region.  Each phase is bracketed
 by HIP events on the library's stream.  `value` is the RKL2 throughput in
 cell-stage updates per second over the RKL2 phases; the BE solve times are
@@ -34,7 +35,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="shell128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phases", default="rkl2,jacobi,ilu0",
+    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32",
                     help="comma list of timed phases (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="before the steps, run a plain device copy of 4 fields (known bytes) "
@@ -77,8 +78,12 @@ def main():
     torch.cuda.set_device(0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     T, br, bt, bp = dev(w["T"]), dev(w["br"]), dev(w["bt"]), dev(w["bp"])
+    f32 = torch.float32
+    T32, br32, bt32, bp32 = T.to(f32), br.to(f32), bt.to(f32), bp.to(f32)
     ctx = sts.Context(sts.SPHERICAL, w["rf"], w["thf"], w["phf"], sts.SHELL_BC)
     ctx.set_dirichlet(0, value=w["T_inner"])
+    ctx32 = sts.Context(sts.SPHERICAL, w["rf"], w["thf"], w["phf"], sts.SHELL_BC)
+    ctx32.set_dirichlet(0, value=w["T_inner"])
     u = torch.empty_like(T)
     x = torch.empty_like(T)
     ncell = T.numel()
@@ -94,7 +99,7 @@ def main():
         del src, dst
 
     def step(rec):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
         ev[0].record(stream)
         ctx.set_spitzer(T, w["kappa0"], br, bt, bp)
         dte = ctx.dt_euler()
@@ -115,8 +120,23 @@ def main():
             iti, _, _ = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_BLOCK_ILU0, block=wl.block,
                                          rtol=wl.rtol)
         ev[4].record(stream)
+        it32 = 0
+        if "fp32" in phases:
+            # precision form: FP32 coefficient set-up, RKL2 step, Jacobi-PCG solve
+            ctx32.set_spitzer_f32(T32, w["kappa0"], br32, bt32, bp32)
+            dt32 = wl.dt_factor * ctx32.dt_euler()
+            ev[5].record(stream)
+            u.copy_(T)
+            ctx32.rkl2_step(u, dt32)
+            ev[6].record(stream)
+            x.copy_(T)
+            it32, _, _ = ctx32.be_pcg_solve(T, x, dt32, pc=sts.PC_JACOBI, rtol=wl.rtol)
+        else:
+            ev[5].record(stream)
+            ev[6].record(stream)
+        ev[7].record(stream)
         if rec is not None:
-            rec.append((ev, s, itj, iti))
+            rec.append((ev, s, itj, iti, it32))
 
     for _ in range(args.warmup):
         step(None)
@@ -127,9 +147,9 @@ def main():
         step(recs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ph = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(4)] for r in recs])  # ms
+    ph = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(7)] for r in recs])  # ms
     s = recs[-1][1]
-    t_setup, t_rk, t_jac, t_ilu = ph.mean(axis=0) / 1e3
+    t_setup, t_rk, t_jac, t_ilu, t_set32, t_rk32, t_jac32 = ph.mean(axis=0) / 1e3
     cell_updates = ncell * s
     value = cell_updates / t_rk if t_rk > 0 else 0.0
     # algorithmic bytes of one RKL2 super-step: stage 1 reads u0 + 6 coefficient
@@ -155,9 +175,18 @@ def main():
                                f"dt = {wl.dt_factor:g} dt_Euler, rtol {wl.rtol:g}",
                    "rkl2_stages": s, "ilu_block": list(wl.block)},
         "phase_ms": {"setup": t_setup * 1e3, "rkl2_step": t_rk * 1e3,
-                     "be_pcg_jacobi": t_jac * 1e3, "be_pcg_ilu0": t_ilu * 1e3},
-        "be_pcg_s_per_solve": {"jacobi": t_jac, "block_ilu0_8x8x8": t_ilu},
-        "be_pcg_iters": {"jacobi": recs[-1][2], "block_ilu0_8x8x8": recs[-1][3]},
+                     "be_pcg_jacobi": t_jac * 1e3, "be_pcg_ilu0": t_ilu * 1e3,
+                     "fp32_setup": t_set32 * 1e3, "fp32_rkl2_step": t_rk32 * 1e3,
+                     "fp32_be_pcg_jacobi": t_jac32 * 1e3},
+        "be_pcg_s_per_solve": {"jacobi": t_jac, "block_ilu0_8x8x8": t_ilu,
+                               "fp32_form_jacobi": t_jac32},
+        "be_pcg_iters": {"jacobi": recs[-1][2], "block_ilu0_8x8x8": recs[-1][3],
+                         "fp32_form_jacobi_inner": recs[-1][4]},
+        "speedup_vs_fp64_jacobi_pcg": {
+            "block_ilu0_8x8x8": t_jac / t_ilu if t_ilu > 0 else None,
+            "fp32_form_jacobi": t_jac / t_jac32 if t_jac32 > 0 else None,
+            "rkl2_step": t_jac / t_rk if t_rk > 0 else None,
+            "fp32_form_rkl2_step": t_jac / t_rk32 if t_rk32 > 0 else None},
         "roofline": {"kernel": "k_stage<OP_SPITZER> (fused 19-point stencil + RKL2 stage)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -167,6 +196,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, wl.dt_factor)
     print(json.dumps(out), flush=True)
     ctx.close()
+    ctx32.close()
 
 
 if __name__ == "__main__":

@@ -79,6 +79,26 @@ sts_status sts_set_spitzer(sts_ctx *ctx, const double *T, double kappa0,
  * times nu (no per-cell coefficient arrays).  */
 sts_status sts_set_isotropic(sts_ctx *ctx, double nu);
 
+/* sts_set_spitzer_f32 - the precision form of sts_set_spitzer: T and the unit
+ * vector b are device FP32 arrays [n0][n1][n2]; the face / edge coefficients
+ * are formed from them (FP64 set-up arithmetic) and stored in FP32.  Until the
+ * next set_* call the context runs the FP32 form:
+ *  - rkl2_step iterates FP32 increments delta_k = u_k - u_0 (stencil and stage
+ *    arithmetic in FP32) and returns u^{n+1} = u_0 + delta_s accumulated in
+ *    FP64 (u stays an FP64 array);
+ *  - be_pcg_solve (Jacobi only) refines in mixed precision: FP64 outer
+ *    residual b - A x (FP32 coefficients widened), FP32-vector inner PCG with
+ *    FP64 dot products, alpha / beta and norms, x += correction in FP64;
+ *    *iters counts inner iterations, *relres is the FP64 true residual;
+ *  - apply_F evaluates F(u) from FP64 u with the FP32 coefficients.
+ * The FP32 form targets <= 1e-6 relative error in T against the FP64
+ * solution (a stated error of the form, not a parity bound).  */
+sts_status sts_set_spitzer_f32(sts_ctx *ctx, const float *T, double kappa0, const float *b0,
+                               const float *b1, const float *b2);
+/* sts_set_isotropic_f32 - the viscosity operator of sts_set_isotropic run in
+ * the FP32 form described above.  */
+sts_status sts_set_isotropic_f32(sts_ctx *ctx, double nu);
+
 /* sts_set_dirichlet - boundary values on axis-0 side `side` (0 = low,
  * 1 = high), used if that side is STS_BC_DIRICHLET: `values` is a device
  * FP64 [n1][n2] array copied into the context, or NULL to use the constant

@@ -34,5 +34,7 @@ from ._binding import (  # noqa: F401
     sts_dt_euler,
     sts_set_dirichlet,
     sts_set_isotropic,
+    sts_set_isotropic_f32,
     sts_set_spitzer,
+    sts_set_spitzer_f32,
 )

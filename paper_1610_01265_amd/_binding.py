@@ -49,6 +49,8 @@ def load():
         "sts_num_cells": (ctypes.c_longlong, [P]),
         "sts_set_spitzer": (I, [P, P, D, P, P, P]),
         "sts_set_isotropic": (I, [P, D]),
+        "sts_set_spitzer_f32": (I, [P, P, D, P, P, P]),
+        "sts_set_isotropic_f32": (I, [P, D]),
         "sts_set_dirichlet": (I, [P, I, P, D]),
         "sts_dt_euler": (I, [P, PD]),
         "apply_F": (I, [P, P, P, I]),
@@ -66,8 +68,9 @@ def load():
 
 def exported_symbols():
     return ["sts_create", "sts_destroy", "sts_set_stream", "sts_last_error", "sts_num_cells",
-            "sts_set_spitzer", "sts_set_isotropic", "sts_set_dirichlet", "sts_dt_euler",
-            "apply_F", "rkl2_step", "be_pcg_solve", "sts_be_residual"]
+            "sts_set_spitzer", "sts_set_isotropic", "sts_set_spitzer_f32", "sts_set_isotropic_f32",
+            "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "be_pcg_solve",
+            "sts_be_residual"]
 
 
 def _ptr(t: torch.Tensor | None, ncell: int, name: str, ncomp: int | None = 1,
@@ -143,6 +146,18 @@ class Context:
         self._sync_stream()
         self._check(self._lib.sts_set_isotropic(self._h, float(nu)))
 
+    def set_spitzer_f32(self, T, kappa0, b0, b1, b2):
+        """Precision form: T, b are float32 device tensors."""
+        self._sync_stream()
+        n, f = self.ncell, torch.float32
+        self._check(self._lib.sts_set_spitzer_f32(
+            self._h, _ptr(T, n, "T", dtype=f), float(kappa0), _ptr(b0, n, "b0", dtype=f),
+            _ptr(b1, n, "b1", dtype=f), _ptr(b2, n, "b2", dtype=f)))
+
+    def set_isotropic_f32(self, nu):
+        self._sync_stream()
+        self._check(self._lib.sts_set_isotropic_f32(self._h, float(nu)))
+
     def set_dirichlet(self, side, values=None, value=0.0):
         self._sync_stream()
         nb = self.shape[1] * self.shape[2]
@@ -215,6 +230,14 @@ def sts_set_spitzer(ctx: Context, T, kappa0, b0, b1, b2):
 
 def sts_set_isotropic(ctx: Context, nu):
     ctx.set_isotropic(nu)
+
+
+def sts_set_spitzer_f32(ctx: Context, T, kappa0, b0, b1, b2):
+    ctx.set_spitzer_f32(T, kappa0, b0, b1, b2)
+
+
+def sts_set_isotropic_f32(ctx: Context, nu):
+    ctx.set_isotropic_f32(nu)
 
 
 def sts_set_dirichlet(ctx: Context, side, values=None, value=0.0):

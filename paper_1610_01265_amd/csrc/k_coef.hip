@@ -13,13 +13,14 @@ __device__ __forceinline__ double spitzer_kappa(double T, double kappa0) {
   return kappa0 * T * T * sqrt(T);
 }
 
+template <class TI>
 struct SpitzerIn {
-  const double *T, *b0, *b1, *b2;
+  const TI *T, *b0, *b1, *b2;
   double kappa0;
   __device__ __forceinline__ void D(int c, double &d00, double &d11, double &d22, double &d01,
                                     double &d02, double &d12) const {
-    const double kap = spitzer_kappa(T[c], kappa0);
-    const double x = b0[c], y = b1[c], z = b2[c];
+    const double kap = spitzer_kappa((double)T[c], kappa0);
+    const double x = (double)b0[c], y = (double)b1[c], z = (double)b2[c];
     d00 = kap * x * x;
     d11 = kap * y * y;
     d22 = kap * z * z;
@@ -28,15 +29,16 @@ struct SpitzerIn {
     d12 = kap * y * z;
   }
   __device__ __forceinline__ double Dab(int c, int a, int b) const {
-    const double kap = spitzer_kappa(T[c], kappa0);
-    const double *p[3] = {b0, b1, b2};
-    return kap * p[a][c] * p[b][c];
+    const double kap = spitzer_kappa((double)T[c], kappa0);
+    const TI *p[3] = {b0, b1, b2};
+    return kap * (double)p[a][c] * (double)p[b][c];
   }
 };
 
 // w_a(c) = A_a Dbar_aa / dl_a on the +a face; K_ab(c) = W_e Dbar_ab on the
 // edge with origin c (W_e, Dbar_ab: means over the edge's four cells).
-__global__ void __launch_bounds__(TX *TY) k_spitzer_coef(Grid g, SpitzerIn in, double *w0,
+template <class TI>
+__global__ void __launch_bounds__(TX *TY) k_spitzer_coef(Grid g, SpitzerIn<TI> in, double *w0,
                                                          double *w1, double *w2, double *k01,
                                                          double *k02, double *k12) {
   const int k = blockIdx.x * TX + threadIdx.x;
@@ -96,7 +98,8 @@ __global__ void __launch_bounds__(TX *TY) k_spitzer_coef(Grid g, SpitzerIn in, d
 
 // Dirichlet face weight w_b = A_b D_00(c) / (distance centre -> face) on the
 // axis-0 boundary layers; D_00 = kappa b_0^2 (conduction) or nu (isotropic).
-__global__ void k_dirichlet_w(Grid g, int op, const double *T, const double *b0, double kappa0,
+template <class TI>
+__global__ void k_dirichlet_w(Grid g, int op, const TI *T, const TI *b0, double kappa0,
                               double nu, double *wb_lo, double *wb_hi) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.n1 * g.n2) return;
@@ -107,7 +110,7 @@ __global__ void k_dirichlet_w(Grid g, int op, const double *T, const double *b0,
     double d = nu;
     if (op == OP_SPITZER) {
       const int c = lin(g, i, j, k);
-      d = spitzer_kappa(T[c], kappa0) * b0[c] * b0[c];
+      d = spitzer_kappa((double)T[c], kappa0) * (double)b0[c] * (double)b0[c];
     }
     const double w = (side ? g.ab_hi : g.ab_lo) * a * d / (side ? g.db_hi : g.db_lo);
     (side ? wb_hi : wb_lo)[t] = w;
@@ -156,13 +159,20 @@ __global__ void k_fill(double *p, long long n, double v) {
   if (t < n) p[t] = v;
 }
 
+__global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ b, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) b[t] = (float)a[t];
+}
+
 // flag |= 1 if any T is not finite and positive or any b is not finite
-__global__ void k_check_spitzer(long long n, const double *T, const double *b0,
-                                const double *b1, const double *b2, int *flag) {
+template <class TI>
+__global__ void k_check_spitzer(long long n, const TI *T, const TI *b0, const TI *b1,
+                                const TI *b2, int *flag) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const double x = T[t];
-  const bool ok = isfinite(x) && x > 0.0 && isfinite(b0[t]) && isfinite(b1[t]) && isfinite(b2[t]);
+  const double x = (double)T[t];
+  const bool ok = isfinite(x) && x > 0.0 && isfinite((double)b0[t]) && isfinite((double)b1[t]) &&
+                  isfinite((double)b2[t]);
   if (!ok) atomicOr(flag, 1);
 }
 
@@ -172,24 +182,38 @@ dim3 grid3(const sts_ctx *c) {
 
 }  // namespace
 
-void launch_spitzer_coef(const sts_ctx *c, const double *T, double kappa0, const double *b0,
-                         const double *b1, const double *b2) {
+template <class TI>
+void spitzer_coef(const sts_ctx *c, const TI *T, double kappa0, const TI *b0, const TI *b1,
+                  const TI *b2) {
   const long long n = c->ncell;
-  SpitzerIn in{T, b0, b1, b2, kappa0};
+  SpitzerIn<TI> in{T, b0, b1, b2, kappa0};
   double *w = c->d_w;
-  hipLaunchKernelGGL(k_spitzer_coef, grid3(c), dim3(TX, TY), 0, c->stream, c->grid(), in, w,
+  hipLaunchKernelGGL(k_spitzer_coef<TI>, grid3(c), dim3(TX, TY), 0, c->stream, c->grid(), in, w,
                      w + n, w + 2 * n, w + 3 * n, w + 4 * n, w + 5 * n);
   const int nb = c->n1 * c->n2;
-  hipLaunchKernelGGL(k_dirichlet_w, dim3((nb + 255) / 256), dim3(256), 0, c->stream, c->grid(),
-                     (int)OP_SPITZER, T, b0, kappa0, 0.0, c->d_bnd, c->d_bnd + nb);
+  hipLaunchKernelGGL(k_dirichlet_w<TI>, dim3((nb + 255) / 256), dim3(256), 0, c->stream,
+                     c->grid(), (int)OP_SPITZER, T, b0, kappa0, 0.0, c->d_bnd, c->d_bnd + nb);
+}
+
+void launch_spitzer_coef(const sts_ctx *c, const double *T, double kappa0, const double *b0,
+                         const double *b1, const double *b2) {
+  spitzer_coef<double>(c, T, kappa0, b0, b1, b2);
+}
+
+void launch_spitzer_coef_f32(const sts_ctx *c, const float *T, double kappa0, const float *b0,
+                             const float *b1, const float *b2) {
+  spitzer_coef<float>(c, T, kappa0, b0, b1, b2);
+  const long long n = 6 * c->ncell;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->d_w,
+                     c->d_wf, n);
 }
 
 void launch_dirichlet_weights(const sts_ctx *c) {
   // isotropic operator: weights from geometry and nu only
   const int nb = c->n1 * c->n2;
-  hipLaunchKernelGGL(k_dirichlet_w, dim3((nb + 255) / 256), dim3(256), 0, c->stream, c->grid(),
-                     (int)OP_ISOTROPIC, (const double *)nullptr, (const double *)nullptr, 0.0,
-                     c->nu, c->d_bnd, c->d_bnd + nb);
+  hipLaunchKernelGGL(k_dirichlet_w<double>, dim3((nb + 255) / 256), dim3(256), 0, c->stream,
+                     c->grid(), (int)OP_ISOTROPIC, (const double *)nullptr,
+                     (const double *)nullptr, 0.0, c->nu, c->d_bnd, c->d_bnd + nb);
 }
 
 void launch_sdiag(const sts_ctx *c) {
@@ -209,8 +233,15 @@ void launch_fill(const sts_ctx *c, double *p, long long n, double v) {
 void launch_check_spitzer(const sts_ctx *c, const double *T, const double *b0, const double *b1,
                           const double *b2, int *flag) {
   const long long n = c->ncell;
-  hipLaunchKernelGGL(k_check_spitzer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                     n, T, b0, b1, b2, flag);
+  hipLaunchKernelGGL(k_check_spitzer<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     c->stream, n, T, b0, b1, b2, flag);
+}
+
+void launch_check_spitzer_f32(const sts_ctx *c, const float *T, const float *b0, const float *b1,
+                              const float *b2, int *flag) {
+  const long long n = c->ncell;
+  hipLaunchKernelGGL(k_check_spitzer<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     c->stream, n, T, b0, b1, b2, flag);
 }
 
 int gershgorin_parts(const sts_ctx *c) {

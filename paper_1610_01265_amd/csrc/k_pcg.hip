@@ -154,6 +154,56 @@ __global__ void k_fin_beta(const double *part, int n, long long cap, PcgScalars 
   }
 }
 
+// FP32 form inner solve: r = (float) r64, 1/A_ii in FP32, e = 0, p = z;
+// partial sums r.z (region 0) and r.r (region 1).
+__global__ void __launch_bounds__(NT)
+    k_f32_init(long long n, const double *__restrict__ r64, const double *__restrict__ invd64,
+               float *__restrict__ r, float *__restrict__ invd, float *__restrict__ e,
+               double *part, long long cap) {
+  double rz = 0.0, rr = 0.0;
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
+    const float rv = (float)r64[c], iv = (float)invd64[c];
+    r[c] = rv;
+    invd[c] = iv;
+    e[c] = 0.0f;
+    rz += (double)rv * (double)(rv * iv);
+    rr += (double)rv * (double)rv;
+  }
+  wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(NT)
+    k_f32_pass_b(long long n, float *__restrict__ e, const float *__restrict__ p,
+                 float *__restrict__ r, const float *__restrict__ y,
+                 const float *__restrict__ invd, double *part, long long cap,
+                 const PcgScalars *sc) {
+  if (sc->done) return;
+  const float alpha = (float)sc->alpha;
+  double rz = 0.0, rr = 0.0;
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
+    e[c] = e[c] + alpha * p[c];
+    const float rn = r[c] - alpha * y[c];
+    r[c] = rn;
+    rz += (double)rn * (double)(rn * invd[c]);
+    rr += (double)rn * (double)rn;
+  }
+  wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(NT) k_f32_add(long long n, double *__restrict__ x,
+                                                const float *__restrict__ e) {
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride)
+    x[c] = x[c] + (double)e[c];
+}
+
+__global__ void k_fill_f32(float *p, long long n, float v) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
 __global__ void k_sum2(const double *part, int n, long long cap, double *out) {
   __shared__ double a, b;
   block_sum_parts(part, n, cap, &a, &b);
@@ -195,6 +245,13 @@ void launch_init_p(const sts_ctx *c, const double *r, const double *invd, const 
                      r, invd, zilu, p, part);
 }
 
+void launch_finalize_init_n(const sts_ctx *c, const double *pb, int nb, const double *prr,
+                            int nrr, const double *prz, int nrz, PcgScalars *sc, double rtol,
+                            int maxit) {
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(256), 0, c->stream, pb, nb, prr, nrr, prz, nrz, sc,
+                     rtol, maxit);
+}
+
 void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr,
                            const double *prz, PcgScalars *sc, double rtol, int maxit) {
   const int n3 = stencil_parts(c);
@@ -227,5 +284,31 @@ void launch_sum2(const sts_ctx *c, const double *part, int nparts, double *out2)
   hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, c->stream, part, nparts, cap_of(c), out2);
 }
 
+
+}  // namespace sts
+
+namespace sts {
+
+void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, float *r,
+                    float *invd, float *e, double *part) {
+  hipLaunchKernelGGL(k_f32_init, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, r64,
+                     invd64, r, invd, e, part, (long long)c->red_cap);
+}
+
+void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const float *y,
+                const float *invd, double *part, const PcgScalars *sc) {
+  hipLaunchKernelGGL(k_f32_pass_b, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, e, p,
+                     r, y, invd, part, (long long)c->red_cap, sc);
+}
+
+void f32_add_to(const sts_ctx *c, double *x, const float *e) {
+  hipLaunchKernelGGL(k_f32_add, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, x, e);
+}
+
+void launch_fill_f32(const sts_ctx *c, float *p, long long n, float v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p,
+                     n, v);
+}
 
 }  // namespace sts

@@ -20,6 +20,8 @@
 #include "k_common.h"
 #include "k_reduce.h"
 
+#include <type_traits>
+
 namespace sts {
 
 namespace {
@@ -34,7 +36,17 @@ constexpr int TK = 64, TJ = STS_MARCH_TJ, NT = TK * TJ;
 constexpr int HK = TK + 2, HJ = TJ + 2, PL = HK * HJ;  // one LDS plane (tile + halo)
 constexpr int NLOAD = (PL + NT - 1) / NT;
 
-enum { M_F = 0, M_RK1 = 1, M_RK = 2, M_PA = 3, M_RES = 4, M_RESN = 5 };
+enum {
+  M_F = 0,      // out = F(u)
+  M_RK1 = 1,    // RKL2 stage 1: F0 = F(u_0), out = u_0 + mu~_1 dt F0
+  M_RK = 2,     // RKL2 stage k >= 2
+  M_PA = 3,     // PCG pass A: p, y = A p, partial p.y
+  M_RES = 4,    // r = b - A x, partial r.r, b.b
+  M_RESN = 5,   // partial norms of b - A x only
+  M_F0F = 6,    // FP32 form: F0 = F(u_0) evaluated in FP64, stored FP32
+  M_DK = 7,     // FP32 form stage k: delta_k from delta_{k-1}, delta_{k-2}, F0
+  M_DLAST = 8   // FP32 form last stage: u^{n+1} = u_0 + delta_s (FP64)
+};
 
 // Index along an axis for a position that may lie outside [0, n): periodic
 // axes wrap (a tile may be wider than a short axis, so use a full modulo),
@@ -48,75 +60,108 @@ __device__ __forceinline__ int wrapclamp(int x, int n, int per) {
   return x < 0 ? 0 : n - 1;
 }
 
+template <class T>
 struct LoadU {
-  const double *__restrict__ u;
+  using value_type = T;
+  const T *__restrict__ u;
   __device__ __forceinline__ void prepare() {}
-  __device__ __forceinline__ double operator()(long long idx) const { return u[idx]; }
+  __device__ __forceinline__ T operator()(long long idx) const { return u[idx]; }
 };
 
 // p = z + beta p_old with z = r / A_ii (Jacobi) or a stored block-ILU0 z.
-template <int PC>
+template <int PC, class T>
 struct LoadP {
-  const double *__restrict__ r;
-  const double *__restrict__ invd;
-  const double *__restrict__ zilu;
-  const double *__restrict__ pold;
+  using value_type = T;
+  const T *__restrict__ r;
+  const T *__restrict__ invd;
+  const T *__restrict__ zilu;
+  const T *__restrict__ pold;
   const PcgScalars *sc;
   int first;
-  double beta;
-  __device__ __forceinline__ void prepare() { beta = first ? 0.0 : sc->beta; }
-  __device__ __forceinline__ double operator()(long long idx) const {
-    const double z = (PC == STS_PC_JACOBI) ? r[idx] * invd[idx] : zilu[idx];
+  T beta;
+  __device__ __forceinline__ void prepare() { beta = first ? T(0) : T(sc->beta); }
+  __device__ __forceinline__ T operator()(long long idx) const {
+    const T z = (PC == STS_PC_JACOBI) ? r[idx] * invd[idx] : zilu[idx];
     return first ? z : z + beta * pold[idx];
   }
 };
 
+// Coefficient arrays of the conduction operator in storage type CT.
+template <class CT>
+struct CoefS {
+  const CT *w0, *w1, *w2, *k01, *k02, *k12;
+  const double *wb_lo, *wb_hi, *ub_lo, *ub_hi;
+  double nu;
+};
+
+// Operands of the consumer of F; their element types depend on the mode.
 struct Args {
-  double *out;         // F, u_k, p (pass A), r (residual)
-  double *F0;          // RKL2 F(u_0)
-  const double *ukm2;  // RKL2 u_{k-2}
-  const double *u0;    // RKL2 u_0
+  void *out;           // F, u_k, delta_k, p (pass A), r (residual), u^{n+1}
+  void *F0;            // RKL2 F(u_0)
+  const void *ukm2;    // RKL2 u_{k-2} / delta_{k-2}
+  const double *u0;    // RKL2 u_0 (FP64)
   const double *b;     // residual: right-hand side
-  double *y;           // pass A: A p
+  void *y;             // pass A: A p
   double *part;        // per-workgroup partial sums (two regions of cap)
   long long cap;
   double mu, nu, mut_dt, gt_dt, dt;
   const PcgScalars *sc;
 };
 
+template <class R>
 struct PlaneGeo {
   Nb A;
-  double s00m, s00, s10m, s10, s10p, s20m, s20, s20p, v0;
-  double a00m, a00;  // isotropic: A00[i-1], A00[i]
-  double a10, a20;   // isotropic: A10[i], A20[i]
+  R s00m, s00, s10m, s10, s10p, s20m, s20, s20p, v0;
+  R a00m, a00;  // isotropic: A00[i-1], A00[i]
+  R a10, a20;   // isotropic: A10[i], A20[i]
   int dIm;
 };
 
+template <class R>
 struct ThreadGeo {
   Nb B, C;
-  double t11m, t11, t21m, t21, t21p, t22m, t22, v12;
-  double a01, a02, a01m, a11, a11m, a12, a21, a22, a22m;  // isotropic area factors
+  R t11m, t11, t21m, t21, t21p, t22m, t22, v12;
+  R a01, a02, a01m, a11, a11m, a12, a21, a22, a22m;  // isotropic area factors
   int dJm, dKm;
 };
 
-// (S u)_c (+ g_c when WITH_G), u read through U(di, dj, dk).
-template <int OP, bool WITH_G, class UF>
-__device__ __forceinline__ double apply_S(const Grid &g, const Coef &C, const UF &U, int i, int j,
-                                          int k, int c, const PlaneGeo &pg,
-                                          const ThreadGeo &tg) {
-  const double u0 = U(0, 0, 0);
-  double acc;
+template <class R>
+struct EdgeG {
+  R ia0, ia1, ib0, ib1;
+};
+
+// Contribution of one edge to (S u)_c for the cell at role (p, q).
+template <class R>
+__device__ __forceinline__ R edge_term_r(R K, R u00, R u10, R u01, R u11, const EdgeG<R> &e,
+                                         int p, int q) {
+  const R h = R(0.5);
+  const R X = h * ((u10 - u00) * e.ia0 + (u11 - u01) * e.ia1);
+  const R Y = h * ((u01 - u00) * e.ib0 + (u11 - u10) * e.ib1);
+  const R ya = (q ? e.ia1 : e.ia0) * Y;
+  const R xb = (p ? e.ib1 : e.ib0) * X;
+  return h * K * ((p ? -ya : ya) + (q ? -xb : xb));
+}
+
+// (S u)_c (+ g_c when WITH_G), u read through U(di, dj, dk); arithmetic in R,
+// coefficients stored as CT.
+template <int OP, bool WITH_G, class R, class CT, class UF>
+__device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const UF &U, int i, int j,
+                                     int k, int c, const PlaneGeo<R> &pg,
+                                     const ThreadGeo<R> &tg) {
+  const R u0 = U(0, 0, 0);
+  const R zero = R(0);
+  R acc;
   if (OP == OP_SPITZER) {
     // unconditional coefficient loads (all indices lie inside the grid)
     const int cA = c + pg.dIm, cB = c + tg.dJm, cC = c + tg.dKm;
-    const double w0p = C.w0[c], w0m = C.w0[cA], w1p = C.w1[c], w1m = C.w1[cB];
-    const double w2p = C.w2[c], w2m = C.w2[cC];
-    const double K01[4] = {C.k01[c], C.k01[cA], C.k01[cB], C.k01[cA + tg.dJm]};
-    const double K02[4] = {C.k02[c], C.k02[cA], C.k02[cC], C.k02[cA + tg.dKm]};
-    const double K12[4] = {C.k12[c], C.k12[cB], C.k12[cC], C.k12[cB + tg.dKm]};
-    acc = w0p * (U(1, 0, 0) - u0) + (pg.A.hm ? w0m : 0.0) * (U(-1, 0, 0) - u0);
-    acc += w1p * (U(0, 1, 0) - u0) + (tg.B.hm ? w1m : 0.0) * (U(0, -1, 0) - u0);
-    acc += w2p * (U(0, 0, 1) - u0) + (tg.C.hm ? w2m : 0.0) * (U(0, 0, -1) - u0);
+    const R w0p = C.w0[c], w0m = C.w0[cA], w1p = C.w1[c], w1m = C.w1[cB];
+    const R w2p = C.w2[c], w2m = C.w2[cC];
+    const R K01[4] = {R(C.k01[c]), R(C.k01[cA]), R(C.k01[cB]), R(C.k01[cA + tg.dJm])};
+    const R K02[4] = {R(C.k02[c]), R(C.k02[cA]), R(C.k02[cC]), R(C.k02[cA + tg.dKm])};
+    const R K12[4] = {R(C.k12[c]), R(C.k12[cB]), R(C.k12[cC]), R(C.k12[cB + tg.dKm])};
+    acc = w0p * (U(1, 0, 0) - u0) + (pg.A.hm ? w0m : zero) * (U(-1, 0, 0) - u0);
+    acc += w1p * (U(0, 1, 0) - u0) + (tg.B.hm ? w1m : zero) * (U(0, -1, 0) - u0);
+    acc += w2p * (U(0, 0, 1) - u0) + (tg.C.hm ? w2m : zero) * (U(0, 0, -1) - u0);
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -125,68 +170,70 @@ __device__ __forceinline__ double apply_S(const Grid &g, const Coef &C, const UF
         // plane (0, 1)
         {
           const bool ex = (p ? pg.A.hm : pg.A.hp) && (q ? tg.B.hm : tg.B.hp);
-          EdgeGeo e;
+          EdgeG<R> e;
           e.ia0 = e.ia1 = p ? pg.s00m : pg.s00;
-          const double tj = q ? tg.t11m : tg.t11;
+          const R tj = q ? tg.t11m : tg.t11;
           e.ib0 = (p ? pg.s10m : pg.s10) * tj;
           e.ib1 = (p ? pg.s10 : pg.s10p) * tj;
-          acc += edge_term(ex ? K01[r] : 0.0, U(-p, -q, 0), U(1 - p, -q, 0), U(-p, 1 - q, 0),
-                           U(1 - p, 1 - q, 0), e, p, q);
+          acc += edge_term_r<R>(ex ? K01[r] : zero, U(-p, -q, 0), U(1 - p, -q, 0),
+                                U(-p, 1 - q, 0), U(1 - p, 1 - q, 0), e, p, q);
         }
         // plane (0, 2)
         {
           const bool ex = (p ? pg.A.hm : pg.A.hp) && (q ? tg.C.hm : tg.C.hp);
-          EdgeGeo e;
+          EdgeG<R> e;
           e.ia0 = e.ia1 = p ? pg.s00m : pg.s00;
-          const double tk = q ? tg.t22m : tg.t22;
+          const R tk = q ? tg.t22m : tg.t22;
           e.ib0 = (p ? pg.s20m : pg.s20) * tg.t21 * tk;
           e.ib1 = (p ? pg.s20 : pg.s20p) * tg.t21 * tk;
-          acc += edge_term(ex ? K02[r] : 0.0, U(-p, 0, -q), U(1 - p, 0, -q), U(-p, 0, 1 - q),
-                           U(1 - p, 0, 1 - q), e, p, q);
+          acc += edge_term_r<R>(ex ? K02[r] : zero, U(-p, 0, -q), U(1 - p, 0, -q),
+                                U(-p, 0, 1 - q), U(1 - p, 0, 1 - q), e, p, q);
         }
         // plane (1, 2)
         {
           const bool ex = (p ? tg.B.hm : tg.B.hp) && (q ? tg.C.hm : tg.C.hp);
-          EdgeGeo e;
+          EdgeG<R> e;
           e.ia0 = e.ia1 = pg.s10 * (p ? tg.t11m : tg.t11);
-          const double tk = q ? tg.t22m : tg.t22;
+          const R tk = q ? tg.t22m : tg.t22;
           e.ib0 = pg.s20 * (p ? tg.t21m : tg.t21) * tk;
           e.ib1 = pg.s20 * (p ? tg.t21 : tg.t21p) * tk;
-          acc += edge_term(ex ? K12[r] : 0.0, U(0, -p, -q), U(0, 1 - p, -q), U(0, -p, 1 - q),
-                           U(0, 1 - p, 1 - q), e, p, q);
+          acc += edge_term_r<R>(ex ? K12[r] : zero, U(0, -p, -q), U(0, 1 - p, -q),
+                                U(0, -p, 1 - q), U(0, 1 - p, 1 - q), e, p, q);
         }
       }
   } else {
     // nu * (area / distance) on each face, from the separable tables
-    const double w0p = pg.a00 * tg.a01 * tg.a02 * pg.s00;
-    const double w0m = pg.a00m * tg.a01 * tg.a02 * pg.s00m;
-    const double w1p = pg.a10 * tg.a11 * tg.a12 * (pg.s10 * tg.t11);
-    const double w1m = pg.a10 * tg.a11m * tg.a12 * (pg.s10 * tg.t11m);
-    const double w2p = pg.a20 * tg.a21 * tg.a22 * (pg.s20 * tg.t21 * tg.t22);
-    const double w2m = pg.a20 * tg.a21 * tg.a22m * (pg.s20 * tg.t21 * tg.t22m);
-    acc = w0p * (U(1, 0, 0) - u0) + (pg.A.hm ? w0m : 0.0) * (U(-1, 0, 0) - u0);
-    acc += w1p * (U(0, 1, 0) - u0) + (tg.B.hm ? w1m : 0.0) * (U(0, -1, 0) - u0);
-    acc += w2p * (U(0, 0, 1) - u0) + (tg.C.hm ? w2m : 0.0) * (U(0, 0, -1) - u0);
-    acc *= C.nu;
+    const R w0p = pg.a00 * tg.a01 * tg.a02 * pg.s00;
+    const R w0m = pg.a00m * tg.a01 * tg.a02 * pg.s00m;
+    const R w1p = pg.a10 * tg.a11 * tg.a12 * (pg.s10 * tg.t11);
+    const R w1m = pg.a10 * tg.a11m * tg.a12 * (pg.s10 * tg.t11m);
+    const R w2p = pg.a20 * tg.a21 * tg.a22 * (pg.s20 * tg.t21 * tg.t22);
+    const R w2m = pg.a20 * tg.a21 * tg.a22m * (pg.s20 * tg.t21 * tg.t22m);
+    acc = w0p * (U(1, 0, 0) - u0) + (pg.A.hm ? w0m : zero) * (U(-1, 0, 0) - u0);
+    acc += w1p * (U(0, 1, 0) - u0) + (tg.B.hm ? w1m : zero) * (U(0, -1, 0) - u0);
+    acc += w2p * (U(0, 0, 1) - u0) + (tg.C.hm ? w2m : zero) * (U(0, 0, -1) - u0);
+    acc *= R(C.nu);
   }
   if ((g.dir_lo && i == 0) || (g.dir_hi && i == g.n0 - 1)) {
     const int bi = j * g.n2 + k;
     const bool lo = g.dir_lo && i == 0;
-    const double wb = lo ? C.wb_lo[bi] : C.wb_hi[bi];
-    const double ub = lo ? C.ub_lo[bi] : C.ub_hi[bi];
+    const R wb = lo ? C.wb_lo[bi] : C.wb_hi[bi];
+    const R ub = lo ? C.ub_lo[bi] : C.ub_hi[bi];
     acc += WITH_G ? wb * (ub - u0) : -wb * u0;
     if (g.dir_lo && g.dir_hi && i == 0 && i == g.n0 - 1) {  // single radial cell
-      acc += WITH_G ? C.wb_hi[bi] * (C.ub_hi[bi] - u0) : -C.wb_hi[bi] * u0;
+      const R wh = C.wb_hi[bi], uh = C.ub_hi[bi];
+      acc += WITH_G ? wh * (uh - u0) : -wh * u0;
     }
   }
   return acc;
 }
 
-template <int OP, int MODE, class Loader>
+template <int OP, int MODE, class Loader, class CT>
 __global__ void __launch_bounds__(NT)
-    k_march(Grid g, Coef C, Loader ld, Args a, int CI, int nchunk, long long ncell) {
+    k_march(Grid g, CoefS<CT> C, Loader ld, Args a, int CI, int nchunk, long long ncell) {
+  using R = typename Loader::value_type;
   if (MODE == M_PA && a.sc->done) return;
-  __shared__ double s_u[4][PL];
+  __shared__ R s_u[4][PL];
   ld.prepare();
   const int tk = threadIdx.x, tj = threadIdx.y, tid = tj * TK + tk;
   // XCD-aware order: workgroup w runs on XCD w % 8; each XCD gets a
@@ -210,18 +257,18 @@ __global__ void __launch_bounds__(NT)
     const int hj = e / HK, hk = e - hj * HK;
     hoff[q] = wrapclamp(j0 - 1 + hj, g.n1, g.per1) * g.n2 + wrapclamp(k0 - 1 + hk, g.n2, g.per2);
   }
-  auto load_plane = [&](int ip, double *v) {
+  auto load_plane = [&](int ip, R *v) {
     const long long base = off + (long long)wrapclamp(ip, g.n0, g.per0) * n12;
 #pragma unroll
     for (int q = 0; q < NLOAD; ++q) v[q] = ld(base + hoff[q]);
   };
-  auto store_plane = [&](int ip, const double *v) {
-    double *s = s_u[ip & 3];
+  auto store_plane = [&](int ip, const R *v) {
+    R *s = s_u[ip & 3];
 #pragma unroll
     for (int q = 0; q < NLOAD; ++q)
       if (tid + q * NT < PL) s[tid + q * NT] = v[q];
   };
-  double v[NLOAD];
+  R v[NLOAD];
   load_plane(i0 - 1, v);
   store_plane(i0 - 1, v);
   load_plane(i0, v);
@@ -232,7 +279,7 @@ __global__ void __launch_bounds__(NT)
   const int j = j0 + tj, k = k0 + tk;
   const bool active = j < g.n1 && k < g.n2;
   const int jc = min(j, g.n1 - 1), kc = min(k, g.n2 - 1);
-  ThreadGeo tg;
+  ThreadGeo<R> tg;
   tg.B = nbr(jc, g.n1, g.per1);
   tg.C = nbr(kc, g.n2, g.per2);
   tg.t11m = T1(g, T_IL11, tg.B.m);
@@ -262,7 +309,7 @@ __global__ void __launch_bounds__(NT)
     const bool pre = i + 2 <= i1;
     if (pre) load_plane(i + 2, v);
     if (active) {
-      PlaneGeo pg;
+      PlaneGeo<R> pg;
       pg.A = nbr(i, g.n0, g.per0);
       pg.s00m = T0(g, T_IL00, pg.A.m);
       pg.s00 = T0(g, T_IL00, i);
@@ -281,36 +328,52 @@ __global__ void __launch_bounds__(NT)
         pg.a20 = T0(g, T_A20, i);
       }
       const int base = (tj + 1) * HK + (tk + 1);
-      const double *sm = s_u[(i - 1) & 3], *s0 = s_u[i & 3], *sp = s_u[(i + 1) & 3];
-      auto U = [&](int di, int dj, int dk) -> double {
-        const double *s = di < 0 ? sm : (di > 0 ? sp : s0);
+      const R *sm = s_u[(i - 1) & 3], *s0 = s_u[i & 3], *sp = s_u[(i + 1) & 3];
+      auto U = [&](int di, int dj, int dk) -> R {
+        const R *s = di < 0 ? sm : (di > 0 ? sp : s0);
         return s[base + dj * HK + dk];
       };
       const int c = (i * g.n1 + j) * g.n2 + k;
       const long long cc = off + c;
-      const bool with_g = MODE == M_F || MODE == M_RK1 || MODE == M_RK;
-      const double su = apply_S<OP, with_g>(g, C, U, i, j, k, c, pg, tg);
-      const double V = pg.v0 * tg.v12;
-      const double uc = s0[base];
+      constexpr bool with_g = MODE == M_F || MODE == M_RK1 || MODE == M_RK || MODE == M_F0F;
+      const R su = apply_S<OP, with_g, R, CT>(g, C, U, i, j, k, c, pg, tg);
+      const R V = pg.v0 * tg.v12;
+      const R uc = s0[base];
       if (MODE == M_F) {
-        a.out[cc] = su / V;
+        ((R *)a.out)[cc] = su / V;
+      } else if (MODE == M_F0F) {
+        const float F = (float)(su / V);
+        ((float *)a.F0)[cc] = F;
+        if (a.out) ((float *)a.out)[cc] = (float)a.mut_dt * F;  // delta_1 = mu~_1 dt F0
       } else if (MODE == M_RK1) {
-        const double F = su / V;
-        a.F0[cc] = F;
-        a.out[cc] = uc + a.mut_dt * F;
+        const R F = su / V;
+        ((R *)a.F0)[cc] = F;
+        ((R *)a.out)[cc] = uc + R(a.mut_dt) * F;
       } else if (MODE == M_RK) {
-        const double F = su / V;
-        a.out[cc] = a.mu * uc + a.nu * a.ukm2[cc] + (1.0 - a.mu - a.nu) * a.u0[cc] +
-                    a.mut_dt * F + a.gt_dt * a.F0[cc];
+        const R F = su / V;
+        const R *ukm2 = (const R *)a.ukm2, *F0 = (const R *)a.F0;
+        ((R *)a.out)[cc] = R(a.mu) * uc + R(a.nu) * ukm2[cc] +
+                           (R(1) - R(a.mu) - R(a.nu)) * R(a.u0[cc]) + R(a.mut_dt) * F +
+                           R(a.gt_dt) * F0[cc];
+      } else if (MODE == M_DK || MODE == M_DLAST) {
+        // delta_k = mu delta_{k-1} + nu delta_{k-2} + mu~ dt M delta_{k-1}
+        //           + (mu~ + gamma~) dt F0      (gt_dt carries (mu~ + gamma~) dt)
+        const R *dkm2 = (const R *)a.ukm2, *F0 = (const R *)a.F0;
+        const R d = R(a.mu) * uc + R(a.nu) * dkm2[cc] + R(a.mut_dt) * (su / V) +
+                    R(a.gt_dt) * F0[cc];
+        if (MODE == M_DK)
+          ((R *)a.out)[cc] = d;
+        else
+          ((double *)a.out)[cc] = a.u0[cc] + (double)d;
       } else if (MODE == M_PA) {
-        const double yv = V * uc - a.dt * su;
-        a.out[cc] = uc;
-        a.y[cc] = yv;
-        acc_a += uc * yv;
+        const R yv = V * uc - R(a.dt) * su;
+        ((R *)a.out)[cc] = uc;
+        ((R *)a.y)[cc] = yv;
+        acc_a += (double)uc * (double)yv;
       } else {  // residual r = b - A x
         const double bv = a.b[cc];
-        const double rv = bv - (V * uc - a.dt * su);
-        if (MODE == M_RES) a.out[cc] = rv;
+        const double rv = bv - (double)(V * uc - R(a.dt) * su);
+        if (MODE == M_RES) ((double *)a.out)[cc] = rv;
         acc_a += rv * rv;
         acc_b += bv * bv;
       }
@@ -336,12 +399,33 @@ dim3 march_grid(const sts_ctx *c, int ncomp, int *CI, int *nchunk) {
   return dim3(((c->n2 + TK - 1) / TK) * ((c->n1 + TJ - 1) / TJ) * *nchunk * ncomp);
 }
 
-template <int OP, int MODE, class Loader>
+template <class CT>
+CoefS<CT> coef_of(const sts_ctx *c) {
+  const Coef k = c->coef();
+  CoefS<CT> s;
+  const CT *w = (const CT *)(std::is_same<CT, float>::value ? (const void *)c->d_wf
+                                                              : (const void *)c->d_w);
+  const long long n = c->ncell;
+  s.w0 = w;
+  s.w1 = w ? w + n : nullptr;
+  s.w2 = w ? w + 2 * n : nullptr;
+  s.k01 = w ? w + 3 * n : nullptr;
+  s.k02 = w ? w + 4 * n : nullptr;
+  s.k12 = w ? w + 5 * n : nullptr;
+  s.wb_lo = k.wb_lo;
+  s.wb_hi = k.wb_hi;
+  s.ub_lo = k.ub_lo;
+  s.ub_hi = k.ub_hi;
+  s.nu = k.nu;
+  return s;
+}
+
+template <int OP, int MODE, class CT, class Loader>
 void launch(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
   int CI, nchunk;
   const dim3 grid = march_grid(c, ncomp, &CI, &nchunk);
-  hipLaunchKernelGGL((k_march<OP, MODE, Loader>), grid, dim3(TK, TJ), 0, c->stream, c->grid(),
-                     c->coef(), ld, a, CI, nchunk, c->ncell);
+  hipLaunchKernelGGL((k_march<OP, MODE, Loader, CT>), grid, dim3(TK, TJ), 0, c->stream,
+                     c->grid(), coef_of<CT>(c), ld, a, CI, nchunk, c->ncell);
 }
 
 #ifndef STS_GATHER19
@@ -351,9 +435,9 @@ void launch(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
 template <int MODE, class Loader>
 void launch_op(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
   if (STS_GATHER19 && c->op == OP_SPITZER)
-    launch<OP_SPITZER, MODE>(c, ncomp, ld, a);
+    launch<OP_SPITZER, MODE, double>(c, ncomp, ld, a);
   else
-    launch<OP_ISOTROPIC, MODE>(c, ncomp, ld, a);
+    launch<OP_ISOTROPIC, MODE, double>(c, ncomp, ld, a);
 }
 
 }  // namespace
@@ -393,7 +477,7 @@ void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, con
   a.nu = nu;
   a.mut_dt = mut_dt;
   a.gt_dt = gt_dt;
-  const LoadU ld{ukm1};
+  const LoadU<double> ld{ukm1};
   if (mode == 0)
     launch_op<M_F>(c, ncomp, ld, a);
   else if (mode == 1)
@@ -417,10 +501,10 @@ void launch_pass_a(const sts_ctx *c, double dt, const double *r, const double *i
   a.dt = dt;
   a.sc = sc;
   if (zilu) {
-    const LoadP<STS_PC_BLOCK_ILU0> ld{r, invd, zilu, pold, sc, first, 0.0};
+    const LoadP<STS_PC_BLOCK_ILU0, double> ld{r, invd, zilu, pold, sc, first, 0.0};
     launch_op<M_PA>(c, 1, ld, a);
   } else {
-    const LoadP<STS_PC_JACOBI> ld{r, invd, zilu, pold, sc, first, 0.0};
+    const LoadP<STS_PC_JACOBI, double> ld{r, invd, zilu, pold, sc, first, 0.0};
     launch_op<M_PA>(c, 1, ld, a);
   }
 }
@@ -437,7 +521,7 @@ void launch_residual_init(const sts_ctx *c, const double *b, const double *x, do
   a.part = part;
   a.cap = c->red_cap;
   a.dt = dt;
-  launch_op<M_RES>(c, 1, LoadU{x}, a);
+  launch_op<M_RES>(c, 1, LoadU<double>{x}, a);
 }
 
 void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,
@@ -451,7 +535,85 @@ void launch_true_residual(const sts_ctx *c, const double *b, const double *x, do
   a.part = part;
   a.cap = c->red_cap;
   a.dt = dt;
-  launch_op<M_RESN>(c, 1, LoadU{x}, a);
+  launch_op<M_RESN>(c, 1, LoadU<double>{x}, a);
+}
+
+}  // namespace sts
+
+namespace sts {
+
+// ---------------------------------------------------------------------------
+// FP32 form (coefficients stored FP32; d_wf).  The stage arithmetic is FP32;
+// F(u_0) and the outer residual evaluate the stencil in FP64 from the FP64
+// state with the FP32 coefficients widened.
+// ---------------------------------------------------------------------------
+namespace {
+template <int MODE, class Loader>
+void launch_f32(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
+  if (c->op == OP_SPITZER)
+    launch<OP_SPITZER, MODE, float>(c, ncomp, ld, a);
+  else
+    launch<OP_ISOTROPIC, MODE, float>(c, ncomp, ld, a);
+}
+}  // namespace
+
+void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1, double mut_dt) {
+  Args a{};
+  a.F0 = F0;
+  a.out = d1;
+  a.mut_dt = mut_dt;
+  launch_f32<M_F0F>(c, ncomp, LoadU<double>{u0}, a);
+}
+
+void f32_apply(const sts_ctx *c, int ncomp, const double *u, double *Fu) {
+  Args a{};
+  a.out = Fu;
+  launch_f32<M_F>(c, ncomp, LoadU<double>{u}, a);
+}
+
+void f32_stage(const sts_ctx *c, int last, int ncomp, const float *dkm1, const float *dkm2,
+               const float *F0, void *out, const double *u0, double mu, double nu, double mut_dt,
+               double g_dt) {
+  Args a{};
+  a.out = out;
+  a.ukm2 = dkm2;
+  a.F0 = const_cast<float *>(F0);
+  a.u0 = u0;
+  a.mu = mu;
+  a.nu = nu;
+  a.mut_dt = mut_dt;
+  a.gt_dt = g_dt;
+  if (last)
+    launch_f32<M_DLAST>(c, ncomp, LoadU<float>{dkm1}, a);
+  else
+    launch_f32<M_DK>(c, ncomp, LoadU<float>{dkm1}, a);
+}
+
+void f32_pass_a(const sts_ctx *c, double dt, const float *r, const float *invd, const float *pold,
+                float *pnew, float *y, double *part, const PcgScalars *sc, int first) {
+  Args a{};
+  a.out = pnew;
+  a.y = y;
+  a.part = part;
+  a.cap = c->red_cap;
+  a.dt = dt;
+  a.sc = sc;
+  const LoadP<STS_PC_JACOBI, float> ld{r, invd, nullptr, pold, sc, first, 0.0f};
+  launch_f32<M_PA>(c, 1, ld, a);
+}
+
+void f32_residual(const sts_ctx *c, const double *b, const double *x, double dt, double *r,
+                  double *part) {
+  Args a{};
+  a.out = r;
+  a.b = b;
+  a.part = part;
+  a.cap = c->red_cap;
+  a.dt = dt;
+  if (r)
+    launch_f32<M_RES>(c, 1, LoadU<double>{x}, a);
+  else
+    launch_f32<M_RESN>(c, 1, LoadU<double>{x}, a);
 }
 
 }  // namespace sts

@@ -262,6 +262,9 @@ sts_status sts_destroy(sts_ctx *ctx) {
   dfree(ctx->d_t1);
   dfree(ctx->d_t2);
   dfree(ctx->d_w);
+  dfree(ctx->d_wf);
+  dfree(ctx->d_rk32);
+  dfree(ctx->d_pcg32);
   dfree(ctx->d_sdiag);
   dfree(ctx->d_bnd);
   dfree(ctx->d_rk);
@@ -311,6 +314,7 @@ sts_status sts_set_spitzer(sts_ctx *ctx, const double *T, double kappa0, const d
   if (*(int *)ctx->h_pin) FAIL(STS_EINVAL, "sts_set_spitzer: T must be finite and > 0, b finite");
   if ((st = refresh_dirichlet_values(ctx))) return st;
   ctx->op = OP_SPITZER;
+  ctx->prec = 0;
   ctx->nu = 0.0;
   launch_spitzer_coef(ctx, T, kappa0, b0, b1, b2);
   LAUNCHCHK();
@@ -327,12 +331,48 @@ sts_status sts_set_isotropic(sts_ctx *ctx, double nu) {
   if ((st = dalloc(ctx, (void **)&ctx->d_sdiag, ctx->ncell * 8))) return st;
   if ((st = refresh_dirichlet_values(ctx))) return st;
   ctx->op = OP_ISOTROPIC;
+  ctx->prec = 0;
   ctx->nu = nu;
   launch_dirichlet_weights(ctx);
   LAUNCHCHK();
   launch_sdiag(ctx);
   LAUNCHCHK();
   ctx->dt_euler = -1.0;
+  return STS_OK;
+}
+
+sts_status sts_set_spitzer_f32(sts_ctx *ctx, const float *T, double kappa0, const float *b0,
+                               const float *b1, const float *b2) {
+  if (!ctx) return STS_EINVAL;
+  if (!T || !b0 || !b1 || !b2) FAIL(STS_EINVAL, "sts_set_spitzer_f32: null field");
+  if (!(kappa0 > 0.0) || !std::isfinite(kappa0)) FAIL(STS_EINVAL, "kappa0 must be finite, > 0");
+  sts_status st;
+  if ((st = dalloc(ctx, (void **)&ctx->d_w, 6 * ctx->ncell * 8)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_wf, 6 * ctx->ncell * 4)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_sdiag, ctx->ncell * 8)))
+    return st;
+  HIPCHK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+  launch_check_spitzer_f32(ctx, T, b0, b1, b2, ctx->d_flag);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(ctx->h_pin, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (*(int *)ctx->h_pin) FAIL(STS_EINVAL, "sts_set_spitzer_f32: T must be finite and > 0");
+  if ((st = refresh_dirichlet_values(ctx))) return st;
+  ctx->op = OP_SPITZER;
+  ctx->prec = 1;
+  ctx->nu = 0.0;
+  launch_spitzer_coef_f32(ctx, T, kappa0, b0, b1, b2);
+  LAUNCHCHK();
+  launch_sdiag(ctx);
+  LAUNCHCHK();
+  ctx->dt_euler = -1.0;
+  return STS_OK;
+}
+
+sts_status sts_set_isotropic_f32(sts_ctx *ctx, double nu) {
+  sts_status st = sts_set_isotropic(ctx, nu);
+  if (st) return st;
+  ctx->prec = 1;
   return STS_OK;
 }
 
@@ -392,8 +432,49 @@ sts_status apply_F(sts_ctx *ctx, const double *u, double *Fu, int ncomp) {
   if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
   if (!u || !Fu || u == Fu) FAIL(STS_EINVAL, "apply_F: null or aliased arrays");
   if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, "apply_F: ncomp must be in [1, 16]");
-  launch_stage(ctx, 0, ncomp, u, nullptr, nullptr, nullptr, Fu, 0, 0, 0, 0);
+  if (ctx->prec == 1)
+    f32_apply(ctx, ncomp, u, Fu);
+  else
+    launch_stage(ctx, 0, ncomp, u, nullptr, nullptr, nullptr, Fu, 0, 0, 0, 0);
   LAUNCHCHK();
+  return STS_OK;
+}
+
+// FP32 form of the super-step: increments delta_k = u_k - u_0 in FP32,
+//   delta_1 = mu~_1 dt F0,
+//   delta_k = mu_k delta_{k-1} + nu_k delta_{k-2} + mu~_k dt M delta_{k-1}
+//             + (mu~_k + gamma~_k) dt F0,
+// (F affine: F(u_{k-1}) = F0 + M delta_{k-1}), u^{n+1} = u_0 + delta_s in FP64.
+static sts_status rkl2_step_f32(sts_ctx *ctx, double *u, int ncomp, double dt, int s) {
+  const long long n = ctx->ncell * ncomp;
+  if (ctx->rk32_ncomp < ncomp) {
+    dfree(ctx->d_rk32);
+    ctx->rk32_ncomp = 0;
+    sts_status st = dalloc(ctx, (void **)&ctx->d_rk32, (size_t)3 * n * 4);
+    if (st) return st;
+    ctx->rk32_ncomp = ncomp;
+  }
+  float *F0 = ctx->d_rk32, *Da = ctx->d_rk32 + n, *Db = ctx->d_rk32 + 2 * n;
+  const double ss = (double)s * s + s - 2.0;
+  auto bk = [](int k) { return k <= 2 ? 1.0 / 3.0 : ((double)k * k + k - 2.0) / (2.0 * k * (k + 1.0)); };
+  const double w1 = 4.0 / ss;
+  f32_F0(ctx, ncomp, u, F0, Da, (w1 / 3.0) * dt);
+  LAUNCHCHK();
+  for (int k = 2; k <= s; ++k) {
+    const double b = bk(k), b1 = bk(k - 1), b2 = bk(k - 2);
+    const double mu = (2.0 * k - 1.0) / k * b / b1;
+    const double nu = -(k - 1.0) / k * b / b2;
+    const double mut = 4.0 * (2.0 * k - 1.0) / (k * ss) * b / b1;
+    const double gt = -(1.0 - b1) * mut;
+    const float *dkm1 = ((k - 1) & 1) ? Da : Db;
+    // delta_0 = 0: at k = 2 the nu term vanishes (any finite buffer is read)
+    const float *dkm2 = (k == 2) ? Da : (((k - 2) & 1) ? Da : Db);
+    const double nuk = (k == 2) ? 0.0 : nu;
+    const bool last = k == s;
+    void *out = last ? (void *)u : (void *)((k & 1) ? Da : Db);
+    f32_stage(ctx, last, ncomp, dkm1, dkm2, F0, out, u, mu, nuk, mut * dt, (mut + gt) * dt);
+    LAUNCHCHK();
+  }
   return STS_OK;
 }
 
@@ -412,6 +493,8 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
     s = stage_count(ratio);
   }
   if (s < 2 || s > kMaxStages) FAIL(STS_EINVAL, "rkl2_step: s must be >= 2");
+  if (s_used) *s_used = s;
+  if (ctx->prec == 1) return rkl2_step_f32(ctx, u, ncomp, dt, s);
   const long long n = ctx->ncell * ncomp;
   if (ctx->rk_ncomp < ncomp) {
     dfree(ctx->d_rk);
@@ -439,7 +522,6 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
     launch_stage(ctx, 2, ncomp, ukm1, ukm2, u, F0, out, mu, nu, mut * dt, gt * dt);
     LAUNCHCHK();
   }
-  if (s_used) *s_used = s;
   return STS_OK;
 }
 
@@ -464,6 +546,74 @@ static sts_status pcg_workspace(sts_ctx *ctx, int pc, const int block[3], double
   return STS_OK;
 }
 
+// FP32 form of BE + Jacobi-PCG: mixed-precision iterative refinement.  The
+// outer residual r = b - A x is formed in FP64 (FP32 coefficients widened);
+// the correction A e = r is solved by PCG with FP32 vectors and FP64 dot
+// products / alpha / beta / norms to a loose relative tolerance; x += e.
+// Stops when the FP64 residual meets rtol; *iters counts inner iterations.
+constexpr double kInnerTol = 1e-4;
+constexpr int kMaxOuter = 30;
+static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, double dt,
+                                   double rtol, int maxit, int *iters, double *relres) {
+  double *fac;
+  const int one[3] = {1, 1, 1};
+  sts_status st = pcg_workspace(ctx, STS_PC_JACOBI, one, &fac);
+  if (st) return st;
+  const long long n = ctx->ncell, cap = ctx->red_cap;
+  if ((st = dalloc(ctx, (void **)&ctx->d_pcg32, (size_t)6 * n * 4))) return st;
+  double *b = ctx->d_pcg, *invd = b + n, *r64 = b + 2 * n;
+  float *iv = ctx->d_pcg32, *e = iv + n, *r = iv + 2 * n, *p0 = iv + 3 * n, *p1 = iv + 4 * n,
+        *y = iv + 5 * n;
+  double *part = ctx->d_red;
+  PcgScalars *sc = ctx->d_sc, *h = (PcgScalars *)ctx->h_pin;
+  launch_be_rhs(ctx, u_n, dt, b, invd, part + 2 * cap);
+  LAUNCHCHK();
+  const int np3 = stencil_parts(ctx), np1 = pass_b_parts(ctx);
+  int total = 0;
+  double rel = 1.0;
+  for (int outer = 0; outer < kMaxOuter; ++outer) {
+    f32_residual(ctx, b, x, dt, r64, part);
+    launch_sum2(ctx, part, np3, ctx->d_tmp);
+    LAUNCHCHK();
+    double hh[2];
+    HIPCHK(hipMemcpyAsync(hh, ctx->d_tmp, 16, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    rel = hh[1] > 0 ? std::sqrt(hh[0] / hh[1]) : 0.0;
+    if (!std::isfinite(rel)) FAIL(STS_BREAKDOWN, "FP32 form: non-finite residual");
+    if (rel <= rtol || total >= maxit) break;
+    f32_inner_init(ctx, r64, invd, r, iv, e, part);
+    launch_finalize_init_n(ctx, part + cap, np1, part + cap, np1, part, np1, sc, kInnerTol,
+                           maxit - total);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    float *pold = p0, *pnew = p1;
+    for (int it = 0; it < maxit - total && !h->done; ++it) {
+      f32_pass_a(ctx, dt, r, iv, pold, pnew, y, part, sc, it == 0);
+      launch_finalize_alpha(ctx, part, np3, sc);
+      f32_pass_b(ctx, e, pnew, r, y, iv, part, sc);
+      launch_finalize_beta(ctx, part, np1, sc);
+      LAUNCHCHK();
+      std::swap(pold, pnew);
+      if ((it + 1) % kPollEvery == 0 || it + 1 == maxit - total) {
+        HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (h->status == -4) FAIL(STS_BREAKDOWN, "FP32 form: inner PCG breakdown");
+    total += h->iters;
+    f32_add_to(ctx, x, e);
+    LAUNCHCHK();
+  }
+  if (iters) *iters = total;
+  if (relres) *relres = rel;
+  if (rel <= rtol) return STS_OK;
+  ctx->err = "PCG reached maxit";
+  return STS_NOT_CONVERGED;
+}
+
 sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, int pc,
                         const int block[3], double rtol, int maxit, int *iters, double *relres) {
   if (!ctx) return STS_EINVAL;
@@ -480,6 +630,10 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
       if (block[a] < 1 || block[a] > 8) FAIL(STS_EINVAL, "ILU0 block sizes must be in [1, 8]");
       blk[a] = block[a];
     }
+  }
+  if (ctx->prec == 1) {
+    if (pc != STS_PC_JACOBI) FAIL(STS_EINVAL, "the FP32 form supports the Jacobi preconditioner");
+    return be_pcg_solve_f32(ctx, u_n, x, dt, rtol, maxit, iters, relres);
   }
   double *fac;
   sts_status st = pcg_workspace(ctx, pc, blk, &fac);

@@ -81,6 +81,8 @@ struct sts_ctx {
   int op = sts::OP_NONE;
   double nu = 0.0;
   double *d_w = nullptr;      // 6 * ncell: w0 w1 w2 k01 k02 k12
+  float *d_wf = nullptr;      // FP32 copy of d_w (precision form)
+  int prec = 0;               // 0: FP64, 1: FP32 storage (precision form)
   double *d_sdiag = nullptr;  // S_cc (homogeneous diagonal) per cell
   double *d_bnd = nullptr;    // 4 * n1*n2: wb_lo wb_hi ub_lo ub_hi
   double ub_const[2] = {0.0, 0.0};
@@ -90,6 +92,9 @@ struct sts_ctx {
   // workspace
   double *d_rk = nullptr;     // RKL2: F0, Ya, Yb (3 * ncell * ncomp_cap)
   int rk_ncomp = 0;
+  float *d_rk32 = nullptr;    // FP32 form RKL2: F0, delta_a, delta_b
+  int rk32_ncomp = 0;
+  float *d_pcg32 = nullptr;   // FP32 form PCG: 1/A_ii, e, r, p0, p1, y
   double *d_pcg = nullptr;    // PCG vectors
   double *d_red = nullptr;    // reduction partials
   int red_cap = 0;
@@ -110,6 +115,10 @@ namespace sts {
 // geometry / coefficient setup (k_coef.hip)
 void launch_spitzer_coef(const sts_ctx *c, const double *T, double kappa0, const double *b0,
                          const double *b1, const double *b2);
+void launch_spitzer_coef_f32(const sts_ctx *c, const float *T, double kappa0, const float *b0,
+                             const float *b1, const float *b2);
+void launch_check_spitzer_f32(const sts_ctx *c, const float *T, const float *b0, const float *b1,
+                              const float *b2, int *flag);
 void launch_dirichlet_weights(const sts_ctx *c);
 void launch_sdiag(const sts_ctx *c);
 void launch_gershgorin(const sts_ctx *c, double *partials, int nparts);
@@ -122,6 +131,23 @@ void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, con
                   const double *u0, double *F0, double *out, double mu, double nu, double mut_dt,
                   double gt_dt);
 
+// FP32 form (k_stencil.hip, k_pcg.hip)
+void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1, double mut_dt);
+void f32_apply(const sts_ctx *c, int ncomp, const double *u, double *Fu);
+void f32_stage(const sts_ctx *c, int last, int ncomp, const float *dkm1, const float *dkm2,
+               const float *F0, void *out, const double *u0, double mu, double nu, double mut_dt,
+               double g_dt);
+void f32_pass_a(const sts_ctx *c, double dt, const float *r, const float *invd, const float *pold,
+                float *pnew, float *y, double *part, const PcgScalars *sc, int first);
+void f32_residual(const sts_ctx *c, const double *b, const double *x, double dt, double *r,
+                  double *part);
+void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, float *r,
+                    float *invd, float *e, double *part);
+void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const float *y,
+                const float *invd, double *part, const PcgScalars *sc);
+void f32_add_to(const sts_ctx *c, double *x, const float *e);
+void launch_fill_f32(const sts_ctx *c, float *p, long long n, float v);
+
 // PCG (k_pcg.hip).  Partial-sum buffers hold two regions of red_cap values.
 int stencil_parts(const sts_ctx *c);  // workgroups of the 3D-tiled kernels
 int pass_b_parts(const sts_ctx *c);   // workgroups of the 1D kernels
@@ -133,6 +159,9 @@ void launch_residual_init(const sts_ctx *c, const double *b, const double *x, do
                           double *part);
 void launch_init_p(const sts_ctx *c, const double *r, const double *invd, const double *zilu,
                    double *p, double *part);
+void launch_finalize_init_n(const sts_ctx *c, const double *pb, int nb, const double *prr,
+                            int nrr, const double *prz, int nrz, PcgScalars *sc, double rtol,
+                            int maxit);
 void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr,
                            const double *prz, PcgScalars *sc, double rtol, int maxit);
 void launch_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,

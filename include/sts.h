@@ -144,6 +144,114 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
 sts_status sts_be_residual(sts_ctx *ctx, const double *u_n, const double *x, double dt,
                            double *relres);
 
+/* ------------------------------------------------------------------------
+ * Learned initial guess for the backward-Euler solve.
+ *
+ * Not part of the paper: the PCG of Fig. "pcg" (Sec. 2.2) starts from an
+ * initial guess x_0, which the paper takes as u^n.  This network predicts
+ * x_0 from two fields instead.  It is a 3D CNN of `layers` 3x3x3
+ * convolutions, 2 -> 16 -> ... -> 16 -> 1 channels, ReLU between layers,
+ * "same" padding: zero along axes 0 and 1, circular along axis 2.  Inputs:
+ *   channel 0 = dt F(T_prev) * rhs_scale   (the BE increment of one
+ *               explicit step, F as in apply_F with the context's operator)
+ *   channel 1 = (T_prev - T_shift) * T_scale
+ * Output d; the guess is x_0 = T_prev + delta_scale * d.
+ * Arithmetic: BF16 weights and activations, FP32 accumulation on the MFMA
+ * units (v_mfma_f32_16x16x32_bf16), FP32 master weights and Adam state.
+ * Activations are stored channel-last, bf16 [cells][16] (16 channels per
+ * cell, unused channels zero); the first layer's 2 inputs and the last
+ * layer's 1 output are padded to 16 channels with zero weights.
+ *
+ * Host weight vector (cnn_set_weights / cnn_get_weights), FP32, per layer l
+ * with c_in = (l == 0 ? 2 : 16), c_out = (l == last ? 1 : 16):
+ *   W[c_out][c_in][3][3][3]   (kernel offsets a, b, c in -1..1 along axes
+ *                              0, 1, 2, at index [a+1][b+1][c+1]; the
+ *                              output at a cell sums W * input(cell + (a,b,c)))
+ *   bias[c_out]
+ * layers = 4 gives 15169 values.  A new network holds zeros.
+ * The sts_cnn handle uses its context's grid and stream; destroy it before
+ * the context.  It allocates its workspace (about 7 x 32 bytes per cell)
+ * at cnn_create.
+ * ------------------------------------------------------------------------ */
+typedef struct sts_cnn sts_cnn; /* opaque */
+
+/* cnn_create - network of `layers` (2..8) convolutions with `channels` (16)
+ * hidden channels on ctx's grid.  */
+sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels);
+sts_status cnn_destroy(sts_cnn *net);
+
+/* cnn_num_params - length of the host weight vector.  */
+long long cnn_num_params(const sts_cnn *net);
+
+/* cnn_set_weights / cnn_get_weights - copy the FP32 weight vector from / to
+ * the HOST array w[n] (n must equal cnn_num_params).  Setting resets the
+ * Adam state (moments and step count).  Synchronise the stream.  */
+sts_status cnn_set_weights(sts_cnn *net, const float *w, long long n);
+sts_status cnn_get_weights(sts_cnn *net, float *w, long long n);
+
+/* cnn_set_norm - the four input / output scalings above (finite; the
+ * scales nonzero).  Defaults 1, 0, 1, 1.  */
+sts_status cnn_set_norm(sts_cnn *net, double rhs_scale, double T_shift, double T_scale,
+                        double delta_scale);
+
+/* cnn_moments - mean and root-mean-square of scale * (x - y) over the cells
+ * (y may be NULL: read as 0) into the HOST array out[2], FP64 sums in a
+ * fixed order.  A helper for choosing the scalings.  Synchronises.  */
+sts_status cnn_moments(sts_cnn *net, const double *x, const double *y, double scale,
+                       double out[2]);
+
+/* cnn_pack_input - network input x16 (bf16 [cells][16]) from F_prev =
+ * F(T_prev) (as apply_F returns it), dt and T_prev, with the set scalings:
+ * x16[c][0] = bf16(float(dt F_prev[c] rhs_scale)),
+ * x16[c][1] = bf16(float((T_prev[c] - T_shift) T_scale)), others 0.  */
+sts_status cnn_pack_input(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
+                          void *x16);
+
+/* cnn_conv - one convolution of layer `layer` with the current weights
+ * (rounded to bf16), on in16 (bf16 [cells][16]):
+ *   kind 0: out = bf16 [cells][16], ReLU(conv + bias)        (hidden layer)
+ *   kind 1: out = FP32 [cells],     channel 0 of conv + bias (output layer)
+ *   kind 2: out = bf16 [cells][16], adjoint convolution (input gradient:
+ *           transposed channels, mirrored offsets) times (mask16 > 0);
+ *           mask16 NULL: no mask
+ *   kind 3: out = FP32 [cells][16], conv + bias
+ *   kind 4: out = FP32 [cells][16], adjoint convolution, no mask
+ * in16 and out must not overlap.  */
+sts_status cnn_conv(sts_cnn *net, int layer, int kind, const void *in16, const void *mask16,
+                    void *out);
+
+/* cnn_weight_grad - gradient of a scalar loss with respect to layer
+ * `layer`'s padded parameters, given the layer input act16 and the gradient
+ * dout16 with respect to its output (both bf16 [cells][16]):
+ *   grad[(co*16 + ci)*27 + t] = sum_cells dout16[cell][co] act16[cell + off(t)][ci]
+ *   grad[16*16*27 + co]       = sum_cells dout16[cell][co]
+ * (t = 9(a+1) + 3(b+1) + (c+1)), grad a DEVICE FP32 array of 6928 values.
+ * FP32 sums in a fixed order.  */
+sts_status cnn_weight_grad(sts_cnn *net, int layer, const void *act16, const void *dout16,
+                           float *grad);
+
+/* cnn_forward - x0 = T_prev + delta_scale * network(F_prev, dt, T_prev).  */
+sts_status cnn_forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
+                       double *x0);
+
+/* cnn_train_step - one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, rate lr)
+ * on the loss mean_cells (d - (x_star - T_prev) / delta_scale)^2, with
+ * gradients by back-propagation through the same kernels.  *loss (may be
+ * NULL; then the call does not synchronise) receives the loss before the
+ * step.  */
+sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
+                          const double *x_star, float lr, double *loss);
+
+/* cnn_guess - the initial guess for be_pcg_solve(ctx, T_prev, x0, dt, ...)
+ * with the context's current operator: F_prev = F(T_prev), the network's
+ * guess, and a fallback: x0 = T_prev instead when the network's guess is
+ * non-finite or has a larger BE residual than T_prev.  *used_net (may be
+ * NULL) receives 1 if the network's guess was kept; relres[2] (may be NULL)
+ * the relative residuals of the network's guess and of T_prev.
+ * Synchronises the stream.  */
+sts_status cnn_guess(sts_cnn *net, const double *T_prev, double dt, double *x0, int *used_net,
+                     double relres[2]);
+
 #ifdef __cplusplus
 }
 #endif

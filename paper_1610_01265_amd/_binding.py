@@ -57,6 +57,19 @@ def load():
         "rkl2_step": (I, [P, P, I, D, I, PI]),
         "be_pcg_solve": (I, [P, P, P, D, I, PI, D, I, PI, PD]),
         "sts_be_residual": (I, [P, P, P, D, PD]),
+        "cnn_create": (I, [ctypes.POINTER(P), P, I, I]),
+        "cnn_destroy": (I, [P]),
+        "cnn_num_params": (ctypes.c_longlong, [P]),
+        "cnn_set_weights": (I, [P, P, ctypes.c_longlong]),
+        "cnn_get_weights": (I, [P, P, ctypes.c_longlong]),
+        "cnn_set_norm": (I, [P, D, D, D, D]),
+        "cnn_moments": (I, [P, P, P, D, PD]),
+        "cnn_pack_input": (I, [P, P, D, P, P]),
+        "cnn_conv": (I, [P, I, I, P, P, P]),
+        "cnn_weight_grad": (I, [P, I, P, P, P]),
+        "cnn_forward": (I, [P, P, D, P, P]),
+        "cnn_train_step": (I, [P, P, D, P, P, ctypes.c_float, PD]),
+        "cnn_guess": (I, [P, P, D, P, PI, PD]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -70,7 +83,9 @@ def exported_symbols():
     return ["sts_create", "sts_destroy", "sts_set_stream", "sts_last_error", "sts_num_cells",
             "sts_set_spitzer", "sts_set_isotropic", "sts_set_spitzer_f32", "sts_set_isotropic_f32",
             "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "be_pcg_solve",
-            "sts_be_residual"]
+            "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
+            "cnn_get_weights", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
+            "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_guess"]
 
 
 def _ptr(t: torch.Tensor | None, ncell: int, name: str, ncomp: int | None = 1,
@@ -215,6 +230,136 @@ class Context:
         return rel.value
 
 
+CNN_RELU, CNN_LINEAR, CNN_INPUT_GRAD, CNN_F32, CNN_INPUT_GRAD_F32 = 0, 1, 2, 3, 4
+CNN_PADDED_PARAMS = 16 * 16 * 27 + 16  # per layer, cnn_weight_grad's output
+
+
+class Cnn:
+    """Learned initial guess (sts_cnn): a 3D CNN on the context's grid.
+    Activations are bfloat16 tensors of shape [cells, 16]."""
+
+    def __init__(self, ctx: Context, layers=4, channels=16):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        ctx._sync_stream()
+        ctx._check(self._lib.cnn_create(ctypes.byref(h), ctx._h, int(layers), int(channels)))
+        self._h = h
+        self.layers = layers
+        self.nparam = self._lib.cnn_num_params(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        return self.ctx._check(st)
+
+    def _act(self, t, name, dtype=torch.bfloat16, width=16):
+        return _ptr(t, self.ctx.ncell, name, width, dtype=dtype)
+
+    def set_weights(self, w):
+        import numpy as np
+        self.ctx._sync_stream()
+        a = np.ascontiguousarray(w, dtype=np.float32)
+        self._chk(self._lib.cnn_set_weights(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+
+    def get_weights(self):
+        import numpy as np
+        self.ctx._sync_stream()
+        a = np.empty(self.nparam, np.float32)
+        self._chk(self._lib.cnn_get_weights(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+        return a
+
+    def set_norm(self, rhs_scale, T_shift, T_scale, delta_scale):
+        self._chk(self._lib.cnn_set_norm(self._h, float(rhs_scale), float(T_shift),
+                                         float(T_scale), float(delta_scale)))
+
+    def moments(self, x, y=None, scale=1.0):
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        out = (ctypes.c_double * 2)()
+        self._chk(self._lib.cnn_moments(self._h, _ptr(x, n, "x"), _ptr(y, n, "y"), float(scale),
+                                        out))
+        return out[0], out[1]
+
+    def pack_input(self, F_prev, dt, T_prev, out=None):
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        if out is None:
+            out = torch.empty((n, 16), dtype=torch.bfloat16, device=T_prev.device)
+        self._chk(self._lib.cnn_pack_input(self._h, _ptr(F_prev, n, "F_prev"), float(dt),
+                                           _ptr(T_prev, n, "T_prev"), self._act(out, "out")))
+        return out
+
+    def conv(self, layer, kind, x, mask=None, out=None):
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        if out is None:
+            if kind in (CNN_RELU, CNN_INPUT_GRAD):
+                out = torch.empty((n, 16), dtype=torch.bfloat16, device=x.device)
+            elif kind == CNN_LINEAR:
+                out = torch.empty(n, dtype=torch.float32, device=x.device)
+            else:
+                out = torch.empty((n, 16), dtype=torch.float32, device=x.device)
+        if kind in (CNN_RELU, CNN_INPUT_GRAD):
+            po = self._act(out, "out")
+        elif kind == CNN_LINEAR:
+            po = _ptr(out, n, "out", 1, dtype=torch.float32)
+        else:
+            po = _ptr(out, n, "out", 16, dtype=torch.float32)
+        self._chk(self._lib.cnn_conv(self._h, int(layer), int(kind), self._act(x, "x"),
+                                     self._act(mask, "mask"), po))
+        return out
+
+    def weight_grad(self, layer, act, dout, out=None):
+        self.ctx._sync_stream()
+        if out is None:
+            out = torch.empty(CNN_PADDED_PARAMS, dtype=torch.float32, device=act.device)
+        self._chk(self._lib.cnn_weight_grad(self._h, int(layer), self._act(act, "act"),
+                                            self._act(dout, "dout"),
+                                            _ptr(out, CNN_PADDED_PARAMS, "out", 1,
+                                                 dtype=torch.float32)))
+        return out
+
+    def forward(self, F_prev, dt, T_prev, x0=None):
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        if x0 is None:
+            x0 = torch.empty_like(T_prev)
+        self._chk(self._lib.cnn_forward(self._h, _ptr(F_prev, n, "F_prev"), float(dt),
+                                        _ptr(T_prev, n, "T_prev"), _ptr(x0, n, "x0")))
+        return x0
+
+    def train_step(self, F_prev, dt, T_prev, x_star, lr, want_loss=True):
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        loss = ctypes.c_double()
+        self._chk(self._lib.cnn_train_step(self._h, _ptr(F_prev, n, "F_prev"), float(dt),
+                                           _ptr(T_prev, n, "T_prev"), _ptr(x_star, n, "x_star"),
+                                           float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def guess(self, T_prev, dt, x0=None):
+        """Returns (x0, used_net, (relres_net, relres_prev))."""
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        if x0 is None:
+            x0 = torch.empty_like(T_prev)
+        used = ctypes.c_int()
+        rel = (ctypes.c_double * 2)()
+        self._chk(self._lib.cnn_guess(self._h, _ptr(T_prev, n, "T_prev"), float(dt),
+                                      _ptr(x0, n, "x0"), ctypes.byref(used), rel))
+        return x0, bool(used.value), (rel[0], rel[1])
+
+
 # Module-level names of the C ABI (same names, Python arguments).
 def sts_create(coord, f0, f1, f2, bc=SHELL_BC) -> Context:
     return Context(coord, f0, f1, f2, bc)
@@ -263,3 +408,55 @@ def be_pcg_solve(ctx: Context, u_n, x, dt, pc=PC_JACOBI, block=(8, 8, 8), rtol=1
 
 def sts_be_residual(ctx: Context, u_n, x, dt) -> float:
     return ctx.be_residual(u_n, x, dt)
+
+
+def cnn_create(ctx: Context, layers=4, channels=16) -> Cnn:
+    return Cnn(ctx, layers, channels)
+
+
+def cnn_destroy(net: Cnn):
+    net.close()
+
+
+def cnn_num_params(net: Cnn) -> int:
+    return net.nparam
+
+
+def cnn_set_weights(net: Cnn, w):
+    net.set_weights(w)
+
+
+def cnn_get_weights(net: Cnn):
+    return net.get_weights()
+
+
+def cnn_set_norm(net: Cnn, rhs_scale, T_shift, T_scale, delta_scale):
+    net.set_norm(rhs_scale, T_shift, T_scale, delta_scale)
+
+
+def cnn_moments(net: Cnn, x, y=None, scale=1.0):
+    return net.moments(x, y, scale)
+
+
+def cnn_pack_input(net: Cnn, F_prev, dt, T_prev, out=None):
+    return net.pack_input(F_prev, dt, T_prev, out)
+
+
+def cnn_conv(net: Cnn, layer, kind, x, mask=None, out=None):
+    return net.conv(layer, kind, x, mask, out)
+
+
+def cnn_weight_grad(net: Cnn, layer, act, dout, out=None):
+    return net.weight_grad(layer, act, dout, out)
+
+
+def cnn_forward(net: Cnn, F_prev, dt, T_prev, x0=None):
+    return net.forward(F_prev, dt, T_prev, x0)
+
+
+def cnn_train_step(net: Cnn, F_prev, dt, T_prev, x_star, lr, want_loss=True):
+    return net.train_step(F_prev, dt, T_prev, x_star, lr, want_loss)
+
+
+def cnn_guess(net: Cnn, T_prev, dt, x0=None):
+    return net.guess(T_prev, dt, x0)

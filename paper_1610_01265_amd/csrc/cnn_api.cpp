@@ -1,0 +1,377 @@
+// Host side of the CNN entry points of include/sts.h (learned initial guess
+// of the backward-Euler solve): state, argument checks, weight-vector
+// layout conversion and the launch sequences of inference and training.
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "cnn_internal.h"
+
+using namespace sts;
+
+sts::CnnLaunch sts_cnn::launch() const { return CnnLaunch{ctx->stream, ctx->n0, ctx->n1, ctx->n2}; }
+
+namespace {
+
+#define NFAIL(code, msg)      \
+  do {                        \
+    net->ctx->err = (msg);    \
+    return (code);            \
+  } while (0)
+
+#define NHIPCHK(expr)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      net->ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);          \
+      return STS_EHIP;                                                            \
+    }                                                                             \
+  } while (0)
+
+#define NLAUNCHCHK() NHIPCHK(hipGetLastError())
+
+int in_ch(const sts_cnn *net, int l) { return l == 0 ? 2 : kCnnC; }
+int out_ch(const sts_cnn *net, int l) { return l == net->layers - 1 ? 1 : kCnnC; }
+
+long long count_params(const sts_cnn *net) {
+  long long n = 0;
+  for (int l = 0; l < net->layers; ++l) n += (long long)out_ch(net, l) * (in_ch(net, l) * kCnnTaps + 1);
+  return n;
+}
+
+sts_status nalloc(sts_cnn *net, void **p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    net->ctx->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
+    return STS_ENOMEM;
+  }
+  return STS_OK;
+}
+
+template <class T>
+void nfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+void refresh_frags(sts_cnn *net) {
+  const CnnLaunch L = net->launch();
+  for (int l = 0; l < net->layers; ++l)
+    launch_cnn_make_frags(L, net->d_P + (size_t)l * kCnnPPerLayer, net->frag(l, 0), net->frag(l, 1));
+}
+
+const float *bias(const sts_cnn *net, int l) { return net->d_P + (size_t)l * kCnnPPerLayer + kCnnWPerLayer; }
+
+// network input into act(0), forward through every layer into d_pred
+void forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev) {
+  const CnnLaunch L = net->launch();
+  launch_cnn_pack_input(L, F_prev, T_prev, dt * net->rhs_scale, net->t_shift, net->t_scale,
+                        net->act(0));
+  for (int l = 0; l + 1 < net->layers; ++l)
+    launch_cnn_conv(L, 0, net->act(l), net->frag(l, 0), bias(net, l), nullptr, net->act(l + 1),
+                    nullptr);
+  const int l = net->layers - 1;
+  launch_cnn_conv(L, 1, net->act(l), net->frag(l, 0), bias(net, l), nullptr, nullptr, net->d_pred);
+}
+
+bool finite_nonzero(double x) { return std::isfinite(x) && x != 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
+  if (!out || !ctx) return STS_EINVAL;
+  *out = nullptr;
+  if (layers < 2 || layers > 8) {
+    ctx->err = "cnn_create: layers must be in [2, 8]";
+    return STS_EINVAL;
+  }
+  if (channels != kCnnC) {
+    ctx->err = "cnn_create: only 16 hidden channels are supported";
+    return STS_EINVAL;
+  }
+  sts_cnn *net = new sts_cnn;
+  net->ctx = ctx;
+  net->layers = layers;
+  net->ncell = ctx->ncell;
+  net->nparam = count_params(net);
+  const size_t np = (size_t)layers * kCnnPPerLayer, nc = (size_t)ctx->ncell;
+  sts_status st = STS_OK;
+  auto A = [&](void **p, size_t bytes) {
+    if (st == STS_OK) st = nalloc(net, p, bytes);
+  };
+  A((void **)&net->d_P, np * 4);
+  A((void **)&net->d_M, np * 4);
+  A((void **)&net->d_V, np * 4);
+  A((void **)&net->d_G, np * 4);
+  A((void **)&net->d_mask, np * 4);
+  A(&net->d_frag, (size_t)2 * layers * kCnnFrag * 2);
+  A(&net->d_act, (size_t)layers * nc * kCnnC * 2);
+  A(&net->d_g, (size_t)2 * nc * kCnnC * 2);
+  A((void **)&net->d_pred, nc * 4);
+  A((void **)&net->d_F, nc * 8);
+  A((void **)&net->d_wpart, (size_t)cnn_wgrad_parts() * kCnnTaps * 256 * 4);
+  A((void **)&net->d_bpart, (size_t)256 * kCnnC * 4);
+  const int npart = std::max(cnn_loss_parts(), 2 * cnn_moment_parts());
+  A((void **)&net->d_part, (size_t)npart * 8);
+  A((void **)&net->d_out, 16);
+  if (st != STS_OK) {
+    cnn_destroy(net);
+    return st;
+  }
+  std::vector<float> mask(np, 0.0f);
+  for (int l = 0; l < layers; ++l) {
+    float *m = mask.data() + (size_t)l * kCnnPPerLayer;
+    for (int co = 0; co < out_ch(net, l); ++co) {
+      for (int ci = 0; ci < in_ch(net, l); ++ci)
+        for (int t = 0; t < kCnnTaps; ++t) m[(co * kCnnC + ci) * kCnnTaps + t] = 1.0f;
+      m[kCnnWPerLayer + co] = 1.0f;
+    }
+  }
+  hipStream_t s = ctx->stream;
+  if (hipMemcpyAsync(net->d_mask, mask.data(), np * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemsetAsync(net->d_P, 0, np * 4, s) != hipSuccess ||
+      hipMemsetAsync(net->d_M, 0, np * 4, s) != hipSuccess ||
+      hipMemsetAsync(net->d_V, 0, np * 4, s) != hipSuccess ||
+      hipMemsetAsync(net->d_act, 0, (size_t)layers * nc * kCnnC * 2, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    ctx->err = "cnn_create: initialisation failed";
+    cnn_destroy(net);
+    return STS_EHIP;
+  }
+  refresh_frags(net);
+  if (hipGetLastError() != hipSuccess) {
+    ctx->err = "cnn_create: fragment kernel launch failed";
+    cnn_destroy(net);
+    return STS_EHIP;
+  }
+  *out = net;
+  return STS_OK;
+}
+
+sts_status cnn_destroy(sts_cnn *net) {
+  if (!net) return STS_EINVAL;
+  if (net->ctx && net->ctx->stream) (void)hipStreamSynchronize(net->ctx->stream);
+  nfree(net->d_P);
+  nfree(net->d_M);
+  nfree(net->d_V);
+  nfree(net->d_G);
+  nfree(net->d_mask);
+  nfree(net->d_frag);
+  nfree(net->d_act);
+  nfree(net->d_g);
+  nfree(net->d_pred);
+  nfree(net->d_F);
+  nfree(net->d_wpart);
+  nfree(net->d_bpart);
+  nfree(net->d_part);
+  nfree(net->d_out);
+  delete net;
+  return STS_OK;
+}
+
+long long cnn_num_params(const sts_cnn *net) { return net ? net->nparam : 0; }
+
+sts_status cnn_set_weights(sts_cnn *net, const float *w, long long n) {
+  if (!net) return STS_EINVAL;
+  if (!w || n != net->nparam) NFAIL(STS_EINVAL, "cnn_set_weights: need cnn_num_params values");
+  for (long long q = 0; q < n; ++q)
+    if (!std::isfinite(w[q])) NFAIL(STS_EINVAL, "cnn_set_weights: non-finite weight");
+  const size_t np = (size_t)net->layers * kCnnPPerLayer;
+  std::vector<float> P(np, 0.0f);
+  const float *src = w;
+  for (int l = 0; l < net->layers; ++l) {
+    float *dst = P.data() + (size_t)l * kCnnPPerLayer;
+    const int co_n = out_ch(net, l), ci_n = in_ch(net, l);
+    for (int co = 0; co < co_n; ++co)
+      for (int ci = 0; ci < ci_n; ++ci)
+        for (int t = 0; t < kCnnTaps; ++t) dst[(co * kCnnC + ci) * kCnnTaps + t] = *src++;
+    for (int co = 0; co < co_n; ++co) dst[kCnnWPerLayer + co] = *src++;
+  }
+  hipStream_t s = net->ctx->stream;
+  NHIPCHK(hipMemcpyAsync(net->d_P, P.data(), np * 4, hipMemcpyHostToDevice, s));
+  NHIPCHK(hipMemsetAsync(net->d_M, 0, np * 4, s));
+  NHIPCHK(hipMemsetAsync(net->d_V, 0, np * 4, s));
+  refresh_frags(net);
+  NLAUNCHCHK();
+  NHIPCHK(hipStreamSynchronize(s));
+  net->step = 0;
+  return STS_OK;
+}
+
+sts_status cnn_get_weights(sts_cnn *net, float *w, long long n) {
+  if (!net) return STS_EINVAL;
+  if (!w || n != net->nparam) NFAIL(STS_EINVAL, "cnn_get_weights: need cnn_num_params values");
+  const size_t np = (size_t)net->layers * kCnnPPerLayer;
+  std::vector<float> P(np);
+  NHIPCHK(hipMemcpyAsync(P.data(), net->d_P, np * 4, hipMemcpyDeviceToHost, net->ctx->stream));
+  NHIPCHK(hipStreamSynchronize(net->ctx->stream));
+  float *dst = w;
+  for (int l = 0; l < net->layers; ++l) {
+    const float *src = P.data() + (size_t)l * kCnnPPerLayer;
+    const int co_n = out_ch(net, l), ci_n = in_ch(net, l);
+    for (int co = 0; co < co_n; ++co)
+      for (int ci = 0; ci < ci_n; ++ci)
+        for (int t = 0; t < kCnnTaps; ++t) *dst++ = src[(co * kCnnC + ci) * kCnnTaps + t];
+    for (int co = 0; co < co_n; ++co) *dst++ = src[kCnnWPerLayer + co];
+  }
+  return STS_OK;
+}
+
+sts_status cnn_set_norm(sts_cnn *net, double rhs_scale, double T_shift, double T_scale,
+                        double delta_scale) {
+  if (!net) return STS_EINVAL;
+  if (!finite_nonzero(rhs_scale) || !std::isfinite(T_shift) || !finite_nonzero(T_scale) ||
+      !finite_nonzero(delta_scale))
+    NFAIL(STS_EINVAL, "cnn_set_norm: scalings must be finite and nonzero");
+  net->rhs_scale = rhs_scale;
+  net->t_shift = T_shift;
+  net->t_scale = T_scale;
+  net->delta_scale = delta_scale;
+  return STS_OK;
+}
+
+sts_status cnn_moments(sts_cnn *net, const double *x, const double *y, double scale,
+                       double out[2]) {
+  if (!net) return STS_EINVAL;
+  if (!x || !out || !std::isfinite(scale)) NFAIL(STS_EINVAL, "cnn_moments: bad argument");
+  launch_cnn_moments(net->launch(), x, y, scale, net->d_part, net->d_out);
+  NLAUNCHCHK();
+  double h[2];
+  NHIPCHK(hipMemcpyAsync(h, net->d_out, 16, hipMemcpyDeviceToHost, net->ctx->stream));
+  NHIPCHK(hipStreamSynchronize(net->ctx->stream));
+  const double n = (double)net->ncell;
+  out[0] = h[0] / n;
+  out[1] = std::sqrt(h[1] / n);
+  return STS_OK;
+}
+
+sts_status cnn_pack_input(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
+                          void *x16) {
+  if (!net) return STS_EINVAL;
+  if (!F_prev || !T_prev || !x16) NFAIL(STS_EINVAL, "cnn_pack_input: null array");
+  if (!std::isfinite(dt)) NFAIL(STS_EINVAL, "cnn_pack_input: dt must be finite");
+  launch_cnn_pack_input(net->launch(), F_prev, T_prev, dt * net->rhs_scale, net->t_shift,
+                        net->t_scale, x16);
+  NLAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status cnn_conv(sts_cnn *net, int layer, int kind, const void *in16, const void *mask16,
+                    void *out) {
+  if (!net) return STS_EINVAL;
+  if (layer < 0 || layer >= net->layers) NFAIL(STS_EINVAL, "cnn_conv: layer out of range");
+  if (!in16 || !out || in16 == out) NFAIL(STS_EINVAL, "cnn_conv: null or aliased arrays");
+  const CnnLaunch L = net->launch();
+  const float *b = bias(net, layer);
+  switch (kind) {
+    case 0:
+      launch_cnn_conv(L, 0, in16, net->frag(layer, 0), b, nullptr, out, nullptr);
+      break;
+    case 1:
+      launch_cnn_conv(L, 1, in16, net->frag(layer, 0), b, nullptr, nullptr, (float *)out);
+      break;
+    case 2:
+      launch_cnn_conv(L, 2, in16, net->frag(layer, 1), nullptr, mask16, out, nullptr);
+      break;
+    case 3:
+      launch_cnn_conv(L, 3, in16, net->frag(layer, 0), b, nullptr, nullptr, (float *)out);
+      break;
+    case 4:
+      launch_cnn_conv(L, 3, in16, net->frag(layer, 1), nullptr, nullptr, nullptr, (float *)out);
+      break;
+    default:
+      NFAIL(STS_EINVAL, "cnn_conv: kind must be 0..4");
+  }
+  NLAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status cnn_weight_grad(sts_cnn *net, int layer, const void *act16, const void *dout16,
+                           float *grad) {
+  if (!net) return STS_EINVAL;
+  if (layer < 0 || layer >= net->layers) NFAIL(STS_EINVAL, "cnn_weight_grad: layer out of range");
+  if (!act16 || !dout16 || !grad) NFAIL(STS_EINVAL, "cnn_weight_grad: null array");
+  const CnnLaunch L = net->launch();
+  launch_cnn_wgrad(L, act16, dout16, net->d_wpart, grad);
+  launch_cnn_bgrad(L, dout16, net->d_bpart, grad + kCnnWPerLayer);
+  NLAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status cnn_forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
+                       double *x0) {
+  if (!net) return STS_EINVAL;
+  if (!F_prev || !T_prev || !x0) NFAIL(STS_EINVAL, "cnn_forward: null array");
+  if (!std::isfinite(dt)) NFAIL(STS_EINVAL, "cnn_forward: dt must be finite");
+  forward(net, F_prev, dt, T_prev);
+  launch_cnn_guess(net->launch(), T_prev, net->d_pred, net->delta_scale, x0);
+  NLAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
+                          const double *x_star, float lr, double *loss) {
+  if (!net) return STS_EINVAL;
+  if (!F_prev || !T_prev || !x_star) NFAIL(STS_EINVAL, "cnn_train_step: null array");
+  if (!std::isfinite(dt)) NFAIL(STS_EINVAL, "cnn_train_step: dt must be finite");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) NFAIL(STS_EINVAL, "cnn_train_step: lr must be > 0");
+  const CnnLaunch L = net->launch();
+  forward(net, F_prev, dt, T_prev);
+  launch_cnn_loss(L, net->d_pred, x_star, T_prev, 1.0 / net->delta_scale, net->g(0), net->d_part);
+  if (loss) launch_cnn_sum_parts(L, net->d_part, cnn_loss_parts(), net->d_out);
+  int q = 0;  // g(q): gradient with respect to the output of layer l
+  for (int l = net->layers - 1; l >= 0; --l) {
+    float *G = net->d_G + (size_t)l * kCnnPPerLayer;
+    launch_cnn_wgrad(L, net->act(l), net->g(q), net->d_wpart, G);
+    launch_cnn_bgrad(L, net->g(q), net->d_bpart, G + kCnnWPerLayer);
+    if (l > 0) {
+      launch_cnn_conv(L, 2, net->g(q), net->frag(l, 1), nullptr, net->act(l), net->g(1 - q),
+                      nullptr);
+      q = 1 - q;
+    }
+  }
+  net->step += 1;
+  launch_cnn_adam(L, net->layers * kCnnPPerLayer, net->d_P, net->d_M, net->d_V, net->d_G,
+                  net->d_mask, lr, net->step);
+  refresh_frags(net);
+  NLAUNCHCHK();
+  if (loss) {
+    double h;
+    NHIPCHK(hipMemcpyAsync(&h, net->d_out, 8, hipMemcpyDeviceToHost, net->ctx->stream));
+    NHIPCHK(hipStreamSynchronize(net->ctx->stream));
+    *loss = h / (double)net->ncell;
+  }
+  return STS_OK;
+}
+
+sts_status cnn_guess(sts_cnn *net, const double *T_prev, double dt, double *x0, int *used_net,
+                     double relres[2]) {
+  if (!net) return STS_EINVAL;
+  sts_ctx *ctx = net->ctx;
+  if (!T_prev || !x0 || T_prev == x0) NFAIL(STS_EINVAL, "cnn_guess: null or aliased arrays");
+  if (!(dt > 0.0) || !std::isfinite(dt)) NFAIL(STS_EINVAL, "cnn_guess: dt must be finite, > 0");
+  sts_status st = apply_F(ctx, T_prev, net->d_F, 1);
+  if (st) return st;
+  forward(net, net->d_F, dt, T_prev);
+  launch_cnn_guess(net->launch(), T_prev, net->d_pred, net->delta_scale, x0);
+  NLAUNCHCHK();
+  double r_net = 0.0, r_prev = 0.0;
+  if ((st = sts_be_residual(ctx, T_prev, x0, dt, &r_net))) return st;
+  if ((st = sts_be_residual(ctx, T_prev, T_prev, dt, &r_prev))) return st;
+  const bool keep = std::isfinite(r_net) && r_net <= r_prev;
+  if (!keep)
+    NHIPCHK(hipMemcpyAsync(x0, T_prev, (size_t)net->ncell * 8, hipMemcpyDeviceToDevice,
+                           ctx->stream));
+  NHIPCHK(hipStreamSynchronize(ctx->stream));
+  if (used_net) *used_net = keep ? 1 : 0;
+  if (relres) {
+    relres[0] = r_net;
+    relres[1] = r_prev;
+  }
+  return STS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,459 @@
+// Small 3D CNN for the learned PCG initial guess: BF16 implicit-GEMM
+// convolutions on MFMA (FP32 accumulate), their input / weight gradients,
+// and the element-wise pieces of training (input packing, loss, Adam).
+//
+// Layout: activations and gradients are channel-last BF16 [cells][16]
+// (2-channel inputs and the 1-channel output are padded to 16 channels with
+// zero weights).  A 3x3x3 convolution with "same" padding (zero along r and
+// theta, circular along phi) is the GEMM
+//   out[cell][co] = sum_{tap, ci} W[co][ci][tap] in[cell + off(tap)][ci],
+// M = cells, N = 16, K = 27 * 16.  Each MFMA v_mfma_f32_16x16x32_bf16
+// computes C^T (16 channels x 16 cells) over K = 32 = two taps x 16 input
+// channels:  A = weights (lane l: co = l%16, K = 8(l/16)..+7),
+// B = activations (lane l: cell l%16, K = 8(l/16)..+7, i.e. 8 contiguous
+// channels of one cell), C: lane l holds co = 4(l/16)..+3 of cell l%16.
+// The input gradient is the same convolution with the tap-flipped,
+// channel-transposed weights (zero / circular padding are self-adjoint).
+#include <hip/hip_runtime.h>
+
+#include "k_common.h"
+#include "k_reduce.h"
+#include "cnn_internal.h"
+
+namespace sts {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+namespace {
+
+constexpr int CC = 16;           // channels
+constexpr int NTAP = 27;
+constexpr int NSTEP = 14;        // K steps of two taps (tap 27 = zero padding)
+constexpr int TKC = 64, TJC = 4; // output tile per workgroup plane: 4 rows x 64 cells
+constexpr int HKC = TKC + 2, HJC = TJC + 2;
+constexpr int PLC = HKC * HJC;   // cells per LDS plane (tile + halo)
+
+// epilogues of k_conv (numbers are the cnn_conv kinds of the C ABI)
+enum { CV_RELU = 0, CV_LAST = 1, CV_MASK = 2, CV_F32 = 3 };
+
+struct CnnGrid {
+  int n0, n1, n2;  // phi (axis 2) is circular; r, theta zero-padded
+};
+
+__device__ __forceinline__ int tap_a(int t) { return t / 9 - 1; }
+__device__ __forceinline__ int tap_b(int t) { return (t / 3) % 3 - 1; }
+__device__ __forceinline__ int tap_c(int t) { return t % 3 - 1; }
+
+// Forward-type convolution (also used for the input gradient).
+//   wfrag[s][lane][8]: A fragments, s = K step
+//   mode CV_RELU: out_bf = bf16(max(acc + bias, 0))
+//   mode CV_LAST: outf[cell] = acc(co 0) + bias[0]     (FP32, one channel)
+//   mode CV_MASK: out_bf = bf16(acc * (mask[cell][co] > 0))   (no mask: acc)
+//   mode CV_F32 : outf[cell][co] = acc + bias           (FP32; bias optional)
+template <int MODE>
+__global__ void __launch_bounds__(256)
+    k_conv(CnnGrid g, const __bf16 *__restrict__ in, const __bf16 *__restrict__ wfrag,
+           const float *__restrict__ bias, const __bf16 *__restrict__ mask,
+           __bf16 *__restrict__ out_bf, float *__restrict__ outf, int CI, int nchunk) {
+  __shared__ __attribute__((aligned(16))) __bf16 s_in[3][PLC * CC];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int ntk = (g.n2 + TKC - 1) / TKC, ntj = (g.n1 + TJC - 1) / TJC;
+  const int bx = blockIdx.x % ntk, by = (blockIdx.x / ntk) % ntj, bz = blockIdx.x / (ntk * ntj);
+  const int k0 = bx * TKC, j0 = by * TJC;
+  const int i0 = bz * CI, i1 = min(i0 + CI, g.n0);
+  (void)nchunk;
+  const long long n12 = (long long)g.n1 * g.n2;
+
+  // A fragments (weights) for all K steps: 14 x 8 bf16 per lane
+  bf16x8 wa[NSTEP];
+#pragma unroll
+  for (int s = 0; s < NSTEP; ++s)
+    wa[s] = *reinterpret_cast<const bf16x8 *>(wfrag + ((size_t)s * 64 + lane) * 8);
+
+  // halo-tile loads: PLC cells x 32 B = 2 x 16 B chunks per cell
+  constexpr int NCH = PLC * 2;                 // 16-byte chunks per plane
+  constexpr int NLD = (NCH + 255) / 256;       // per thread
+  int src[NLD];     // cell offset inside a plane (or -1 for zero padding)
+  int dst[NLD];
+#pragma unroll
+  for (int q = 0; q < NLD; ++q) {
+    const int ch = t + q * 256;
+    const int cell = ch >> 1, half = ch & 1;
+    const int hj = cell / HKC, hk = cell - hj * HKC;
+    const int jj = j0 - 1 + hj;
+    int kk = (k0 - 1 + hk) % g.n2;
+    if (kk < 0) kk += g.n2;
+    const bool ok = ch < NCH && jj >= 0 && jj < g.n1;
+    src[q] = ok ? ((jj * g.n2 + kk) * 2 + half) : -1;
+    dst[q] = ch < NCH ? ch : -1;
+  }
+  auto load_plane = [&](int ip, uint4 *v) {
+    const bool pin = ip >= 0 && ip < g.n0;
+    const uint4 *base = reinterpret_cast<const uint4 *>(in + (long long)(pin ? ip : 0) * n12 * CC);
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      uint4 z = {0u, 0u, 0u, 0u};
+      v[q] = (pin && src[q] >= 0) ? base[src[q]] : z;
+    }
+  };
+  auto store_plane = [&](int ip, const uint4 *v) {
+    uint4 *s = reinterpret_cast<uint4 *>(s_in[(ip + 3) % 3]);
+#pragma unroll
+    for (int q = 0; q < NLD; ++q)
+      if (dst[q] >= 0) s[dst[q]] = v[q];
+  };
+  uint4 v[NLD];
+  load_plane(i0 - 1, v);
+  store_plane(i0 - 1, v);
+  load_plane(i0, v);
+  store_plane(i0, v);
+  load_plane(i0 + 1, v);
+  store_plane(i0 + 1, v);
+  __syncthreads();
+
+  const int grp = lane >> 4, cl = lane & 15;
+  const int j = j0 + wv;
+  for (int i = i0; i < i1; ++i) {
+    const bool pre = i + 2 <= i1;
+    if (pre) load_plane(i + 2, v);
+    f32x4 acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+      const int tap = min(2 * s + (grp >> 1), NTAP - 1);  // tap 27 has zero weights
+      const int a = tap_a(tap), b = tap_b(tap), c = tap_c(tap);
+      const bf16x8 *pl = reinterpret_cast<const bf16x8 *>(s_in[(i + a + 3) % 3]);
+      const int rowb = (wv + 1 + b) * HKC + 1 + c + cl;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const bf16x8 bv = pl[(rowb + 16 * nb) * 2 + (grp & 1)];
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc[nb], 0, 0, 0);
+      }
+    }
+    if (j < g.n1) {
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int k = k0 + 16 * nb + cl;
+        if (k >= g.n2) continue;
+        const long long cell = (long long)i * n12 + (long long)j * g.n2 + k;
+        const int co0 = 4 * grp;
+        if (MODE == CV_LAST) {
+          if (grp == 0) outf[cell] = acc[nb][0] + bias[0];
+        } else if (MODE == CV_F32) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            outf[cell * CC + co0 + e] = acc[nb][e] + (bias ? bias[co0 + e] : 0.0f);
+        } else {
+          __bf16 o[4];
+          if (MODE == CV_RELU) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (__bf16)fmaxf(acc[nb][e] + bias[co0 + e], 0.0f);
+          } else {  // CV_MASK
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              o[e] = (__bf16)((!mask || (float)mask[cell * CC + co0 + e] > 0.0f) ? acc[nb][e]
+                                                                                 : 0.0f);
+          }
+          uint2 pk;
+          __builtin_memcpy(&pk, o, 8);
+          *reinterpret_cast<uint2 *>(out_bf + cell * CC + co0) = pk;
+        }
+      }
+    }
+    __syncthreads();
+    if (pre) store_plane(i + 2, v);
+    __syncthreads();
+  }
+}
+
+// Weight gradient, one tap per blockIdx.y:
+//   dW[tap][co][ci] = sum_cells dout[cell][co] act[cell + off(tap)][ci]
+// A = dout (lane: co = l%16, 8 cells), B = act (lane: ci = l%16, 8 cells),
+// C[co][ci].  Each workgroup sweeps rows of 64 cells grid-stride and writes
+// one 16 x 16 partial per tap; k_wgrad_reduce sums the partials in order.
+__global__ void __launch_bounds__(256)
+    k_wgrad(CnnGrid g, const __bf16 *__restrict__ act, const __bf16 *__restrict__ dout,
+            float *__restrict__ part) {
+  __shared__ float red[4][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int tap = blockIdx.y;
+  const int a = tap_a(tap), b = tap_b(tap), c = tap_c(tap);
+  const int grp = lane >> 4, cl = lane & 15;
+  const int rowlen = (g.n2 + 63) / 64;  // 64-cell segments per phi row
+  const long long nrows = (long long)g.n0 * g.n1 * rowlen;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (long long r = (long long)blockIdx.x * 4 + wv; r < nrows; r += (long long)gridDim.x * 4) {
+    const int seg = (int)(r % rowlen);
+    const long long ij = r / rowlen;
+    const int i = (int)(ij / g.n1), j = (int)(ij % g.n1);
+    const int ii = i + a, jj = j + b;
+    const bool rowok = ii >= 0 && ii < g.n0 && jj >= 0 && jj < g.n1;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8 av, bv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = seg * 64 + ks * 32 + grp * 8 + e;
+        const bool kin = k < g.n2;
+        const int kc = kin ? k : 0;
+        const __bf16 zero = (__bf16)0.0f;
+        av[e] = kin ? dout[(((long long)i * g.n1 + j) * g.n2 + kc) * CC + cl] : zero;
+        int ks2 = (kc + c) % g.n2;
+        if (ks2 < 0) ks2 += g.n2;
+        bv[e] = (kin && rowok) ? act[(((long long)ii * g.n1 + jj) * g.n2 + ks2) * CC + cl] : zero;
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+  }
+  // C: lane holds co = 4 grp + e, ci = cl; sum the 4 wavefronts in fixed order
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[wv][(4 * grp + e) * 16 + cl] = acc[e];
+  __syncthreads();
+  const float s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  part[((size_t)blockIdx.x * NTAP + tap) * 256 + t] = s;
+}
+
+// g[co][ci][tap] (the master-weight layout) = sum over workgroups of the
+// partials part[w][tap][co][ci], in workgroup order.
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, float *__restrict__ g) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (co * 16 + ci) * 27 + tap
+  if (idx >= NTAP * 256) return;
+  const int tap = idx % NTAP, cc = idx / NTAP;
+  float s = 0.f;
+  for (int w = 0; w < nwg; ++w) s += part[((size_t)w * NTAP + tap) * 256 + cc];
+  g[idx] = s;
+}
+
+// Bias gradient partials: sum_cells dout[cell][co]
+__global__ void __launch_bounds__(256)
+    k_bgrad(long long ncell, const __bf16 *__restrict__ dout, float *__restrict__ part) {
+  __shared__ float red[256];
+  const int t = threadIdx.x, co = t & 15;
+  float s = 0.f;
+  for (long long c = (long long)blockIdx.x * 16 + (t >> 4); c < ncell; c += (long long)gridDim.x * 16)
+    s += (float)dout[c * CC + co];
+  red[t] = s;
+  __syncthreads();
+  if (t < 16) {
+    float x = 0.f;
+    for (int q = 0; q < 16; ++q) x += red[q * 16 + t];
+    part[blockIdx.x * 16 + t] = x;
+  }
+}
+
+__global__ void k_bgrad_reduce(const float *__restrict__ part, int nwg, float *__restrict__ db) {
+  const int co = threadIdx.x;
+  if (co >= 16) return;
+  float s = 0.f;
+  for (int w = 0; w < nwg; ++w) s += part[w * 16 + co];
+  db[co] = s;
+}
+
+// Network input: channel 0 = rhs * rs, channel 1 = (T - ts) * tsc, others 0.
+__global__ void k_pack_input(long long n, const double *__restrict__ rhs,
+                             const double *__restrict__ T, double rs, double tsh, double tsc,
+                             __bf16 *__restrict__ x) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  __bf16 o[16];
+  o[0] = (__bf16)(float)(rhs[c] * rs);
+  o[1] = (__bf16)(float)((T[c] - tsh) * tsc);
+  for (int q = 2; q < 16; ++q) o[q] = (__bf16)0.0f;
+  uint4 p0, p1;
+  __builtin_memcpy(&p0, o, 16);
+  __builtin_memcpy(&p1, o + 8, 16);
+  reinterpret_cast<uint4 *>(x + c * CC)[0] = p0;
+  reinterpret_cast<uint4 *>(x + c * CC)[1] = p1;
+}
+
+// MSE loss on the normalised increment and its gradient (channel 0).
+//   target = (x_star - T) * inv_sd;  d = pred - target;  loss = mean d^2
+__global__ void __launch_bounds__(256)
+    k_loss(long long n, const float *__restrict__ pred, const double *__restrict__ xs,
+           const double *__restrict__ T, double inv_sd, __bf16 *__restrict__ g,
+           double *__restrict__ part) {
+  double s = 0.0;
+  const float scale = (float)(2.0 / (double)n);
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < n; c += stride) {
+    const double tg = (xs[c] - T[c]) * inv_sd;
+    const double d = (double)pred[c] - tg;
+    s += d * d;
+    __bf16 o[16];
+    o[0] = (__bf16)(scale * (float)d);
+    for (int q = 1; q < 16; ++q) o[q] = (__bf16)0.0f;
+    uint4 p0, p1;
+    __builtin_memcpy(&p0, o, 16);
+    __builtin_memcpy(&p1, o + 8, 16);
+    reinterpret_cast<uint4 *>(g + c * CC)[0] = p0;
+    reinterpret_cast<uint4 *>(g + c * CC)[1] = p1;
+  }
+  wg_sum2<256>(s, 0.0, threadIdx.x, part + blockIdx.x, nullptr);
+}
+
+// x0 = T + sd * pred
+__global__ void k_guess(long long n, const double *__restrict__ T, const float *__restrict__ pred,
+                        double sd, double *__restrict__ x0) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) x0[c] = T[c] + sd * (double)pred[c];
+}
+
+// Adam on FP32 master parameters (gradients masked where the padded network
+// has no parameter: mask[q] = 0).
+__global__ void k_adam(int n, float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, const float *__restrict__ mask, float lr,
+                       float b1, float b2, float c1, float c2, float eps) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float gq = g[q] * mask[q];
+  const float mq = b1 * m[q] + (1.f - b1) * gq;
+  const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+  m[q] = mq;
+  v[q] = vq;
+  p[q] = p[q] - lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// BF16 A fragments from the FP32 master weights W[co][ci][tap] of one layer:
+//   forward: frag[s][l][e] = W[co = l%16][ci = 8((l/16)%2) + e][tap = 2s + (l/16)/2]
+//   input gradient (transposed, tap-flipped):
+//            frag[s][l][e] = W[co = 8((l/16)%2) + e][ci = l%16][26 - tap]
+__global__ void k_make_frags(const float *__restrict__ W, __bf16 *__restrict__ ffwd,
+                             __bf16 *__restrict__ fbwd) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // s * 512 + l * 8 + e
+  if (idx >= NSTEP * 64 * 8) return;
+  const int s = idx / 512, l = (idx / 8) % 64, e = idx % 8;
+  const int g4 = l >> 4, tap = 2 * s + (g4 >> 1);
+  const int r16 = l & 15, c8 = 8 * (g4 & 1) + e;
+  float wf = 0.f, wb = 0.f;
+  if (tap < NTAP) {
+    wf = W[(r16 * CC + c8) * NTAP + tap];
+    wb = W[(c8 * CC + r16) * NTAP + (NTAP - 1 - tap)];
+  }
+  ffwd[idx] = (__bf16)wf;
+  fbwd[idx] = (__bf16)wb;
+}
+
+// Mean and root-mean-square of scale * (x - y) (y optional): partial sums
+// per workgroup, then one workgroup sums them in a fixed order.
+__global__ void __launch_bounds__(256)
+    k_moments(long long n, const double *__restrict__ x, const double *__restrict__ y, double sc,
+              double *__restrict__ part) {
+  double s1 = 0.0, s2 = 0.0;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < n; c += stride) {
+    const double d = sc * (y ? x[c] - y[c] : x[c]);
+    s1 += d;
+    s2 += d * d;
+  }
+  wg_sum2<256>(s1, s2, threadIdx.x, part + blockIdx.x, part + gridDim.x + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256)
+    k_sum_parts(const double *__restrict__ part, int n, int two, double *__restrict__ out) {
+  block_sum_parts(part, n, n, out, two ? out + 1 : nullptr);
+}
+
+int conv_chunk(int n0, int ntiles) {
+  long long ci = (long long)ntiles * n0 / 1024;
+  if (ci < 1) ci = 1;
+  if (ci > 16) ci = 16;
+  return (int)ci;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+void launch_cnn_conv(const CnnLaunch &L, int mode, const void *in, const void *wfrag, const float *bias,
+              const void *mask, void *out_bf, float *outf) {
+  CnnGrid g{L.n0, L.n1, L.n2};
+  const int ntk = (L.n2 + TKC - 1) / TKC, ntj = (L.n1 + TJC - 1) / TJC;
+  const int CI = conv_chunk(L.n0, ntk * ntj);
+  const int nchunk = (L.n0 + CI - 1) / CI;
+  const dim3 grid(ntk * ntj * nchunk), blk(256);
+  const __bf16 *pin = (const __bf16 *)in, *pw = (const __bf16 *)wfrag, *pm = (const __bf16 *)mask;
+  __bf16 *pob = (__bf16 *)out_bf;
+  switch (mode) {
+    case CV_RELU:
+      hipLaunchKernelGGL(k_conv<CV_RELU>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      break;
+    case CV_LAST:
+      hipLaunchKernelGGL(k_conv<CV_LAST>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      break;
+    case CV_MASK:
+      hipLaunchKernelGGL(k_conv<CV_MASK>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      break;
+    default:
+      hipLaunchKernelGGL(k_conv<CV_F32>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+  }
+}
+
+int cnn_wgrad_parts() { return 256; }
+
+void launch_cnn_wgrad(const CnnLaunch &L, const void *act, const void *dout, float *part, float *g) {
+  CnnGrid gr{L.n0, L.n1, L.n2};
+  const int nwg = cnn_wgrad_parts();
+  hipLaunchKernelGGL(k_wgrad, dim3(nwg, NTAP), dim3(256), 0, L.stream, gr, (const __bf16 *)act,
+                     (const __bf16 *)dout, part);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((NTAP * 256 + 255) / 256), dim3(256), 0, L.stream, part,
+                     nwg, g);
+}
+
+void launch_cnn_bgrad(const CnnLaunch &L, const void *dout, float *part, float *db) {
+  const int nwg = 256;
+  const long long n = (long long)L.n0 * L.n1 * L.n2;
+  hipLaunchKernelGGL(k_bgrad, dim3(nwg), dim3(256), 0, L.stream, n, (const __bf16 *)dout, part);
+  hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, L.stream, part, nwg, db);
+}
+
+void launch_cnn_pack_input(const CnnLaunch &L, const double *rhs, const double *T, double rs, double tsh,
+                    double tsc, void *x) {
+  const long long n = (long long)L.n0 * L.n1 * L.n2;
+  hipLaunchKernelGGL(k_pack_input, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.stream, n,
+                     rhs, T, rs, tsh, tsc, (__bf16 *)x);
+}
+
+int cnn_loss_parts() { return 1024; }
+
+void launch_cnn_loss(const CnnLaunch &L, const float *pred, const double *xs, const double *T,
+              double inv_sd, void *g, double *part) {
+  const long long n = (long long)L.n0 * L.n1 * L.n2;
+  hipLaunchKernelGGL(k_loss, dim3(cnn_loss_parts()), dim3(256), 0, L.stream, n, pred, xs, T,
+                     inv_sd, (__bf16 *)g, part);
+}
+
+void launch_cnn_guess(const CnnLaunch &L, const double *T, const float *pred, double sd, double *x0) {
+  const long long n = (long long)L.n0 * L.n1 * L.n2;
+  hipLaunchKernelGGL(k_guess, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.stream, n, T, pred,
+                     sd, x0);
+}
+
+void launch_cnn_adam(const CnnLaunch &L, int n, float *p, float *m, float *v, const float *g,
+              const float *mask, float lr, int step) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, L.stream, n, p, m, v, g, mask,
+                     lr, b1, b2, c1, c2, 1e-8f);
+}
+
+void launch_cnn_make_frags(const CnnLaunch &L, const float *W, void *ffwd, void *fbwd) {
+  hipLaunchKernelGGL(k_make_frags, dim3((NSTEP * 64 * 8 + 255) / 256), dim3(256), 0, L.stream, W,
+                     (__bf16 *)ffwd, (__bf16 *)fbwd);
+}
+
+int cnn_moment_parts() { return 512; }
+
+void launch_cnn_moments(const CnnLaunch &L, const double *x, const double *y, double sc, double *part,
+                 double *out2) {
+  const long long n = (long long)L.n0 * L.n1 * L.n2;
+  const int np = cnn_moment_parts();
+  hipLaunchKernelGGL(k_moments, dim3(np), dim3(256), 0, L.stream, n, x, y, sc, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, L.stream, part, np, 1, out2);
+}
+
+void launch_cnn_sum_parts(const CnnLaunch &L, const double *part, int n, double *out) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, L.stream, part, n, 0, out);
+}
+
+}  // namespace sts

@@ -4,7 +4,8 @@ This package only *generates inputs*: grid face coordinates, temperature,
 magnetic unit vectors and velocity components.  It holds none of the
 method's arithmetic (no diffusivity, geometry factors, fluxes, time
 stepping or solves), so that both the CPU oracle and the GPU library can
-consume the same arrays without sharing any computation.
+consume the same arrays without sharing any computation.  cnn_init draws the
+learned-guess network's initial weights.
 """
 from .shell import (  # noqa: F401
     WORKLOADS,
@@ -18,3 +19,4 @@ from .shell import (  # noqa: F401
     make_workload,
     random_unit_vectors,
 )
+from .cnn_init import he_normal, flatten, unflatten, layer_dims  # noqa: F401,E402

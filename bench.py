@@ -1,20 +1,32 @@
 """Benchmark of the hot path on one MI355X.
 
 One step = one pass of the whole path over the synthetic shell input:
-  coefficient setup (lagged Spitzer diffusivity, face / edge weights,
-  Gershgorin dt_Euler), one RKL2 super-step at dt = f dt_Euler, one BE step
-  solved by Jacobi-PCG and one by block-ILU0(8^3)-PCG, each to the workload's
-  relative residual; then the FP32 precision form of the RKL2 step and of the
-  Jacobi-PCG solve (mixed-precision refinement to the same FP64 residual).
+  * coefficient setup (lagged Spitzer diffusivity, face / edge weights,
+    Gershgorin dt_Euler);
+  * one RKL2 super-step at dt = f dt_Euler;
+  * one BE step solved by Jacobi-PCG and one by block-ILU0(8^3)-PCG, each
+    to the workload's relative residual;
+  * the FP32 precision form: FP32 coefficient setup, RKL2 step, Jacobi-PCG
+    (mixed-precision refinement to the same FP64 residual);
+  * artificial viscosity on a 3-component velocity field: RKL2 step of all
+    three components and one Jacobi-PCG BE solve per component;
+  * the learned initial guess: cnn_guess (network + residual fallback),
+    Jacobi-PCG from that guess, and one training step of the network.
 Inputs are resident in HBM before the timed region.  Each phase is bracketed
 by HIP events on the library's stream.  `value` is the RKL2 throughput in
-cell-stage updates per second over the RKL2 phases; the BE solve times are
-reported beside it.  The roofline entry is for the RKL2 stage kernel (88
-algorithmic bytes per cell per stage).
+cell-stage updates per second; the BE solve times are reported beside it.
+
+The roofline entry is for the RKL2 stage kernel (the fused stencil + stage
+update): algorithmic bytes per launch (72 B/cell for stage 1, 88 B/cell for
+stages 2..s) over the mean launch duration (RKL2 phase time / s).  `traffic`
+is the copy-calibrated HBM byte count per launch from the committed counter
+summary of the same kernel, or null when the kernel's sources have changed
+since those counters were taken.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +38,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_rkl2_stage_shell128_pmc.txt")
+STAGE_SOURCES = ["k_stencil.hip", "k_common.h", "sts_internal.h"]
 
 
 def parse():
@@ -35,60 +49,140 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="shell128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32",
+    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32,visc,learned",
                     help="comma list of timed phases (profiling runs)")
+    ap.add_argument("--learned-train-seeds", type=int, default=24,
+                    help="training pairs (seeds 1..N) for the network before the timed steps")
+    ap.add_argument("--learned-epochs", type=int, default=3)
     ap.add_argument("--copy-calib", action="store_true",
                     help="before the steps, run a plain device copy of 4 fields (known bytes) "
                          "that calibrates the HBM byte counters")
     return ap.parse_args()
 
 
-def cpu_baseline(w, dt_factor):
-    """The oracle as it stands, timed on this host: one RKL2 super-step of the
-    same workload (the bounded sample: one step of s stages)."""
+def stage_source_hash():
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1610_01265_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(ncell):
+    """Copy-calibrated HBM bytes per stage launch from the counter summary,
+    if it was taken on the current kernel sources and the same cell count."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != stage_source_hash():
+            return None
+        if int(kv.get("cells", -1)) != ncell:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, dt_factor, budget_s=12.0, max_steps=8):
+    """The oracle as it stands, timed on this host: RKL2 super-steps of the
+    same workload, repeated until about budget_s seconds (the bounded sample)."""
     from oracle import operator as O
     from oracle import rkl2 as orkl2
     D = O.spitzer_tensor(w["T"], w["kappa0"], w["br"], w["bt"], w["bp"])
     op = O.assemble("spherical", w["rf"], w["thf"], w["phf"], D, O.SHELL_BC, u_lo=w["T_inner"])
     dte = O.gershgorin_dt_euler(op)
     s = orkl2.stage_count(dt_factor)
-    t0 = time.perf_counter()
-    orkl2.rkl2_step(lambda v: O.apply_F(op, v), w["T"], dt_factor * dte, s)
-    t = time.perf_counter() - t0
+    t = 0.0
+    n = 0
+    while n < max_steps and (n == 0 or t < budget_s):
+        t0 = time.perf_counter()
+        orkl2.rkl2_step(lambda v: O.apply_F(op, v), w["T"], dt_factor * dte, s)
+        t += time.perf_counter() - t0
+        n += 1
     cells = w["T"].size
-    return {"value": cells * s / t, "unit": "cell-stage updates/s", "cores": 1,
+    return {"value": n * cells * s / t, "unit": "cell-stage updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"one RKL2 super-step (s={s}) of {w['workload'].name} "
-                      f"({cells} cells), numpy FP64, single thread, {t:.1f} s"}
+            "sample": f"{n} RKL2 super-step(s) (s={s}) of {w['workload'].name} "
+                      f"({cells} cells), numpy FP64, one thread, {t:.1f} s"}
+
+
+class Timer:
+    """Named HIP-event intervals on one stream."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream, self.marks = torch, stream, []
+
+    def mark(self, name):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(self.stream)
+        self.marks.append((name, ev))
+
+    def intervals(self):
+        out = {}
+        for (a, ea), (_, eb) in zip(self.marks, self.marks[1:]):
+            out[a] = out.get(a, 0.0) + ea.elapsed_time(eb)
+        return out  # ms
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
-                                   "design (DESIGN.md), not an implemented path",
+        print(json.dumps({"error": "this build runs on one GPU only; how the path would shard "
+                                   "across GPUs is described, not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     import paper_1610_01265_amd as sts
-    from workloads import make_workload, WORKLOADS
+    from paper_1610_01265_amd import learned
+    from workloads import WORKLOADS, flatten, he_normal, make_workload
 
     wl = WORKLOADS[args.workload]
-    w = make_workload(wl, with_velocity=False)
+    w = make_workload(wl, with_velocity=True)
     torch.cuda.set_device(0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     T, br, bt, bp = dev(w["T"]), dev(w["br"]), dev(w["bt"]), dev(w["bp"])
     f32 = torch.float32
     T32, br32, bt32, bp32 = T.to(f32), br.to(f32), bt.to(f32), bp.to(f32)
-    ctx = sts.Context(sts.SPHERICAL, w["rf"], w["thf"], w["phf"], sts.SHELL_BC)
-    ctx.set_dirichlet(0, value=w["T_inner"])
-    ctx32 = sts.Context(sts.SPHERICAL, w["rf"], w["thf"], w["phf"], sts.SHELL_BC)
-    ctx32.set_dirichlet(0, value=w["T_inner"])
+    v0 = dev(np.stack(w["v"]))
+    nu = w["nu"]
+    phases = args.phases.split(",")
+
+    def shell_ctx(u_lo):
+        c = sts.Context(sts.SPHERICAL, w["rf"], w["thf"], w["phf"], sts.SHELL_BC)
+        c.set_dirichlet(0, value=u_lo)
+        return c
+
+    ctx, ctx32, ctxv = shell_ctx(w["T_inner"]), shell_ctx(w["T_inner"]), shell_ctx(0.0)
     u = torch.empty_like(T)
     x = torch.empty_like(T)
+    v = torch.empty_like(v0)
+    xv = torch.empty_like(T)
     ncell = T.numel()
-    phases = args.phases.split(",")
     stream = torch.cuda.current_stream()
+
+    net = None
+    held = None
+    learned_info = {}
+    if "learned" in phases:
+        # network trained (untimed) on seeds 1..N; the timed steps guess for the
+        # workload's own seed (not a training pair) and train on a held pair
+        net = sts.Cnn(ctx)
+        net.set_weights(flatten(he_normal(4, 16, 0)))
+        prob = learned.Problem((wl.nr, wl.nth, wl.nph))
+        t0 = time.perf_counter()
+        pairs = learned.make_pairs(prob, range(1, 1 + args.learned_train_seeds), wl.dt_factor,
+                                   rtol=1e-10)
+        learned.fit_norm(net, pairs)
+        hist = learned.train(net, pairs, args.learned_epochs, 1e-3)
+        torch.cuda.synchronize()
+        learned_info = {"train_pairs": len(pairs), "epochs": args.learned_epochs,
+                        "loss_per_epoch": hist, "pretrain_s": time.perf_counter() - t0}
+        held = pairs[0]
+        del pairs
 
     if args.copy_calib:
         src = torch.empty(4 * ncell, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -99,44 +193,64 @@ def main():
         del src, dst
 
     def step(rec):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
-        ev[0].record(stream)
+        tm = Timer(torch, stream)
+        info = {}
+        tm.mark("setup")
         ctx.set_spitzer(T, w["kappa0"], br, bt, bp)
-        dte = ctx.dt_euler()
-        dt = wl.dt_factor * dte
-        ev[1].record(stream)
-        s = 0
+        dt = wl.dt_factor * ctx.dt_euler()
+        tm.mark("rkl2")
         if "rkl2" in phases:
             u.copy_(T)
-            s = ctx.rkl2_step(u, dt)
-        ev[2].record(stream)
-        itj = iti = 0
+            info["s"] = ctx.rkl2_step(u, dt)
+        tm.mark("jacobi")
         if "jacobi" in phases:
             x.copy_(T)
-            itj, _, _ = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_JACOBI, rtol=wl.rtol)
-        ev[3].record(stream)
+            info["it_jac"], _, _ = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_JACOBI, rtol=wl.rtol)
+        tm.mark("ilu0")
         if "ilu0" in phases:
             x.copy_(T)
-            iti, _, _ = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_BLOCK_ILU0, block=wl.block,
-                                         rtol=wl.rtol)
-        ev[4].record(stream)
-        it32 = 0
+            info["it_ilu"], _, _ = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_BLOCK_ILU0,
+                                                    block=wl.block, rtol=wl.rtol)
+        tm.mark("fp32_setup")
         if "fp32" in phases:
-            # precision form: FP32 coefficient set-up, RKL2 step, Jacobi-PCG solve
             ctx32.set_spitzer_f32(T32, w["kappa0"], br32, bt32, bp32)
             dt32 = wl.dt_factor * ctx32.dt_euler()
-            ev[5].record(stream)
+        tm.mark("fp32_rkl2")
+        if "fp32" in phases:
             u.copy_(T)
             ctx32.rkl2_step(u, dt32)
-            ev[6].record(stream)
+        tm.mark("fp32_jacobi")
+        if "fp32" in phases:
             x.copy_(T)
-            it32, _, _ = ctx32.be_pcg_solve(T, x, dt32, pc=sts.PC_JACOBI, rtol=wl.rtol)
-        else:
-            ev[5].record(stream)
-            ev[6].record(stream)
-        ev[7].record(stream)
+            info["it_jac32"], _, _ = ctx32.be_pcg_solve(T, x, dt32, pc=sts.PC_JACOBI,
+                                                        rtol=wl.rtol)
+        tm.mark("visc_rkl2")
+        if "visc" in phases:
+            ctxv.set_isotropic(nu)
+            dtv = wl.dt_factor * ctxv.dt_euler()
+            v.copy_(v0)
+            info["s_visc"] = ctxv.rkl2_step(v, dtv)
+        tm.mark("visc_jacobi")
+        if "visc" in phases:
+            its = []
+            for m in range(3):
+                xv.copy_(v0[m])
+                it, _, _ = ctxv.be_pcg_solve(v0[m], xv, dtv, pc=sts.PC_JACOBI, rtol=wl.rtol)
+                its.append(it)
+            info["it_visc"] = its
+        tm.mark("learned_guess")
+        if "learned" in phases:
+            _, used, rel = net.guess(T, dt, x)
+            info["guess_used_net"], info["guess_relres"] = used, rel
+        tm.mark("learned_jacobi")
+        if "learned" in phases:
+            info["it_learned"], _, _ = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_JACOBI, rtol=wl.rtol)
+        tm.mark("learned_train")
+        if "learned" in phases:
+            net.train_step(held.F, held.dt, held.T, held.x_star, 1e-4, want_loss=False)
+        tm.mark("end")
         if rec is not None:
-            rec.append((ev, s, itj, iti, it32))
+            rec.append((tm, info))
 
     for _ in range(args.warmup):
         step(None)
@@ -147,16 +261,24 @@ def main():
         step(recs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ph = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(7)] for r in recs])  # ms
-    s = recs[-1][1]
-    t_setup, t_rk, t_jac, t_ilu, t_set32, t_rk32, t_jac32 = ph.mean(axis=0) / 1e3
-    cell_updates = ncell * s
-    value = cell_updates / t_rk if t_rk > 0 else 0.0
-    # algorithmic bytes of one RKL2 super-step: stage 1 reads u0 + 6 coefficient
-    # arrays and writes F0, u1 (72 B/cell); stages 2..s read u_{k-1}, u_{k-2}, u0,
-    # F0 + 6 coefficients and write u_k (88 B/cell)
+    ph = {}
+    for tm, _ in recs:
+        for k, val in tm.intervals().items():
+            ph[k] = ph.get(k, 0.0) + val / len(recs)
+    info = recs[-1][1]
+    sec = {k: val / 1e3 for k, val in ph.items()}
+    s = info.get("s", 0)
+    t_rk = sec["rkl2"]
+    value = ncell * s / t_rk if s else 0.0
     alg_bytes = (72 + 88 * (s - 1)) * ncell if s else 0
-    achieved = alg_bytes / t_rk / 1e9 if t_rk > 0 else 0.0
+    achieved = alg_bytes / t_rk / 1e9 if s else 0.0
+    traffic = read_traffic(ncell) if s else None
+    t_jac = sec["jacobi"]
+    t_learn = sec["learned_guess"] + sec["learned_jacobi"]
+
+    def ratio(a, b):
+        return a / b if (a > 0 and b > 0) else None
+
     out = {
         "metric": "RKL2 stage cell-updates/s + BE-PCG s/solve at 1e-8 res; % HBM peak",
         "value": value,
@@ -172,31 +294,40 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: spherical shell {wl.nr}x{wl.nth}x{wl.nph} "
                                f"({ncell} cells), Spitzer conduction, tilted dipole b, "
-                               f"dt = {wl.dt_factor:g} dt_Euler, rtol {wl.rtol:g}",
+                               f"dt = {wl.dt_factor:g} dt_Euler, rtol {wl.rtol:g}; viscosity "
+                               f"on 3 velocity components; learned guess (4-layer CNN)",
                    "rkl2_stages": s, "ilu_block": list(wl.block)},
-        "phase_ms": {"setup": t_setup * 1e3, "rkl2_step": t_rk * 1e3,
-                     "be_pcg_jacobi": t_jac * 1e3, "be_pcg_ilu0": t_ilu * 1e3,
-                     "fp32_setup": t_set32 * 1e3, "fp32_rkl2_step": t_rk32 * 1e3,
-                     "fp32_be_pcg_jacobi": t_jac32 * 1e3},
-        "be_pcg_s_per_solve": {"jacobi": t_jac, "block_ilu0_8x8x8": t_ilu,
-                               "fp32_form_jacobi": t_jac32},
-        "be_pcg_iters": {"jacobi": recs[-1][2], "block_ilu0_8x8x8": recs[-1][3],
-                         "fp32_form_jacobi_inner": recs[-1][4]},
+        "phase_ms": ph,
+        "be_pcg_s_per_solve": {"jacobi": t_jac, "block_ilu0_8x8x8": sec["ilu0"],
+                               "fp32_form_jacobi": sec["fp32_jacobi"],
+                               "learned_guess_jacobi": t_learn,
+                               "viscosity_jacobi_per_component": sec["visc_jacobi"] / 3},
+        "be_pcg_iters": {"jacobi": info.get("it_jac"), "block_ilu0_8x8x8": info.get("it_ilu"),
+                         "fp32_form_jacobi_inner": info.get("it_jac32"),
+                         "learned_guess_jacobi": info.get("it_learned"),
+                         "viscosity_jacobi": info.get("it_visc")},
         "speedup_vs_fp64_jacobi_pcg": {
-            "block_ilu0_8x8x8": t_jac / t_ilu if t_ilu > 0 else None,
-            "fp32_form_jacobi": t_jac / t_jac32 if t_jac32 > 0 else None,
-            "rkl2_step": t_jac / t_rk if t_rk > 0 else None,
-            "fp32_form_rkl2_step": t_jac / t_rk32 if t_rk32 > 0 else None},
-        "roofline": {"kernel": "k_stage<OP_SPITZER> (fused 19-point stencil + RKL2 stage)",
+            "block_ilu0_8x8x8": ratio(t_jac, sec["ilu0"]),
+            "fp32_form_jacobi": ratio(t_jac, sec["fp32_jacobi"]),
+            "learned_guess_jacobi": ratio(t_jac, t_learn),
+            "rkl2_step": ratio(t_jac, t_rk),
+            "fp32_form_rkl2_step": ratio(t_jac, sec["fp32_rkl2"])},
+        "learned": dict(learned_info, guess_used_net=info.get("guess_used_net"),
+                        guess_relres_net_prev=info.get("guess_relres"),
+                        train_step_ms=ph.get("learned_train")),
+        "roofline": {"kernel": "k_march (fused 19-point stencil + RKL2 stage update)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_cell_stage": 88},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes / s if s else None,
+                     "mean_launch_us": t_rk / s * 1e6 if s else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, wl.dt_factor)
     print(json.dumps(out), flush=True)
-    ctx.close()
-    ctx32.close()
+    if net is not None:
+        net.close()
+    for c in (ctx, ctx32, ctxv):
+        c.close()
 
 
 if __name__ == "__main__":

@@ -69,11 +69,31 @@ def test_stage_count_odd_option():
     assert rkl2.stage_count(500, odd=True) == 45
 
 
+def _golden_substeps():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_rkl2_substeps.txt")
+    rows = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                name, s, r = line.split()
+                rows[name] = (int(s), float(r))
+    return rows
+
+
 def test_paper_substep_counts_consistent():
-    """195 conduction and 49 viscosity sub-steps (Fig. iters caption) are the
-    stage counts of dt/dt_E just below 9555 and 613 (Eq. rkl2_s)."""
-    assert rkl2.stage_count(9554) == 195
-    assert rkl2.stage_count(612) == 49
+    """The printed average sub-step counts (Fig. iters caption) are stage counts
+    of Eq. rkl2_s: 195 for dt/dt_E in (9457, 9554.5], 49 in (587.5, 612]; the
+    printed maximal ratios (Sec. 6) need at least as many stages as the averages."""
+    g = _golden_substeps()
+    s_c, r_c = g["conduction"]
+    s_v, r_v = g["viscosity"]
+    assert (s_c, s_v) == (195, 49)
+    assert rkl2.stage_count(9554) == s_c and rkl2.stage_count(9458) == s_c
+    assert rkl2.stage_count(9457) == s_c - 1 and rkl2.stage_count(9555) == s_c + 1
+    assert rkl2.stage_count(612) == s_v and rkl2.stage_count(588) == s_v
+    assert rkl2.stage_count(587) == s_v - 1 and rkl2.stage_count(613) == s_v + 1
+    assert rkl2.stage_count(r_c) >= s_c and rkl2.stage_count(r_v) >= s_v
 
 
 @pytest.mark.parametrize("ratio,lo,hi", [(5, 0.3, 0.7), (50, 0.3, 0.7), (500, 0.3, 0.7)])

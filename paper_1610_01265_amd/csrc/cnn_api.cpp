@@ -112,8 +112,7 @@ sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
   A(&net->d_g, (size_t)2 * nc * kCnnC * 2);
   A((void **)&net->d_pred, nc * 4);
   A((void **)&net->d_F, nc * 8);
-  A((void **)&net->d_wpart, (size_t)cnn_wgrad_parts() * kCnnTaps * 256 * 4);
-  A((void **)&net->d_bpart, (size_t)256 * kCnnC * 4);
+  A((void **)&net->d_wpart, (size_t)cnn_wgrad_parts() * (kCnnTaps + 1) * 256 * 4);
   const int npart = std::max(cnn_loss_parts(), 2 * cnn_moment_parts());
   A((void **)&net->d_part, (size_t)npart * 8);
   A((void **)&net->d_out, 16);
@@ -165,7 +164,6 @@ sts_status cnn_destroy(sts_cnn *net) {
   nfree(net->d_pred);
   nfree(net->d_F);
   nfree(net->d_wpart);
-  nfree(net->d_bpart);
   nfree(net->d_part);
   nfree(net->d_out);
   delete net;
@@ -296,7 +294,6 @@ sts_status cnn_weight_grad(sts_cnn *net, int layer, const void *act16, const voi
   if (!act16 || !dout16 || !grad) NFAIL(STS_EINVAL, "cnn_weight_grad: null array");
   const CnnLaunch L = net->launch();
   launch_cnn_wgrad(L, act16, dout16, net->d_wpart, grad);
-  launch_cnn_bgrad(L, dout16, net->d_bpart, grad + kCnnWPerLayer);
   NLAUNCHCHK();
   return STS_OK;
 }
@@ -326,7 +323,6 @@ sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const d
   for (int l = net->layers - 1; l >= 0; --l) {
     float *G = net->d_G + (size_t)l * kCnnPPerLayer;
     launch_cnn_wgrad(L, net->act(l), net->g(q), net->d_wpart, G);
-    launch_cnn_bgrad(L, net->g(q), net->d_bpart, G + kCnnWPerLayer);
     if (l > 0) {
       launch_cnn_conv(L, 2, net->g(q), net->frag(l, 1), nullptr, net->act(l), net->g(1 - q),
                       nullptr);

@@ -25,9 +25,9 @@ struct CnnLaunch {
 void launch_cnn_conv(const CnnLaunch &L, int kind, const void *in, const void *wfrag,
                      const float *bias, const void *mask, void *out_bf, float *outf);
 int cnn_wgrad_parts();
+// weight and bias gradients of one layer into g (padded master layout, 6928 values)
 void launch_cnn_wgrad(const CnnLaunch &L, const void *act, const void *dout, float *part,
                       float *g);
-void launch_cnn_bgrad(const CnnLaunch &L, const void *dout, float *part, float *db);
 void launch_cnn_pack_input(const CnnLaunch &L, const double *rhs, const double *T, double rs,
                            double tsh, double tsc, void *x);
 int cnn_loss_parts();
@@ -60,7 +60,6 @@ struct sts_cnn {
   float *d_pred = nullptr;     // FP32 [cells] network output
   double *d_F = nullptr;       // FP64 [cells] F(T_prev) for cnn_guess
   float *d_wpart = nullptr;    // weight-gradient partials
-  float *d_bpart = nullptr;    // bias-gradient partials
   double *d_part = nullptr;    // loss / moment partials
   double *d_out = nullptr;     // two device scalars read by the host
   double rhs_scale = 1.0, t_shift = 0.0, t_scale = 1.0, delta_scale = 1.0;

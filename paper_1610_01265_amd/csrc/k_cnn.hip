@@ -16,6 +16,8 @@
 // channel-transposed weights (zero / circular padding are self-adjoint).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "k_common.h"
 #include "k_reduce.h"
 #include "cnn_internal.h"
@@ -151,10 +153,13 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int e = 0; e < 4; ++e) o[e] = (__bf16)fmaxf(acc[nb][e] + bias[co0 + e], 0.0f);
           } else {  // CV_MASK
+            __bf16 mk[4] = {(__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f};
+            if (mask) {
+              const uint2 mv = *reinterpret_cast<const uint2 *>(mask + cell * CC + co0);
+              __builtin_memcpy(mk, &mv, 8);
+            }
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              o[e] = (__bf16)((!mask || (float)mask[cell * CC + co0 + e] > 0.0f) ? acc[nb][e]
-                                                                                 : 0.0f);
+            for (int e = 0; e < 4; ++e) o[e] = (__bf16)((float)mk[e] > 0.0f ? acc[nb][e] : 0.0f);
           }
           uint2 pk;
           __builtin_memcpy(&pk, o, 8);
@@ -168,87 +173,148 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Weight gradient, one tap per blockIdx.y:
+// Weight and bias gradients of one layer:
 //   dW[tap][co][ci] = sum_cells dout[cell][co] act[cell + off(tap)][ci]
-// A = dout (lane: co = l%16, 8 cells), B = act (lane: ci = l%16, 8 cells),
-// C[co][ci].  Each workgroup sweeps rows of 64 cells grid-stride and writes
-// one 16 x 16 partial per tap; k_wgrad_reduce sums the partials in order.
+//   db[co]          = sum_cells dout[cell][co]
+// As an MFMA product with K = cells: A = dout (lane: co = l%16, 8 cells),
+// B = act shifted by the tap (lane: ci = l%16, the same 8 cells), C[co][ci];
+// the bias is a 28th product with B = ones.  Workgroups march r-planes of a
+// 4 x 64 tile like the convolution (3-plane LDS ring of the input window,
+// the tile of dout staged per plane) and accumulate all 28 products in
+// registers over the work items they take (grid-stride); each workgroup
+// writes its partial sums, reduced in a fixed order by k_wgrad_reduce.
+// LDS cells are 32 B (16 channels) with a 32-B gap after every 8 cells, so
+// the 2-byte operand reads of the four 16-lane groups fall in disjoint banks.
+__device__ __forceinline__ int lds_cell(int x) { return (x + (x >> 3)) * CC; }
+
+constexpr int PLCP = PLC + (PLC + 7) / 8;        // padded cells of one ring plane
+constexpr int TCP = TJC * TKC + TJC * TKC / 8;   // padded cells of the dout tile
+
 __global__ void __launch_bounds__(256)
     k_wgrad(CnnGrid g, const __bf16 *__restrict__ act, const __bf16 *__restrict__ dout,
-            float *__restrict__ part) {
-  __shared__ float red[4][256];
+            float *__restrict__ part, int CI, int nitems) {
+  __shared__ __attribute__((aligned(16))) __bf16 s_in[3][PLCP * CC];
+  __shared__ __attribute__((aligned(16))) __bf16 s_d[TCP * CC];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int tap = blockIdx.y;
-  const int a = tap_a(tap), b = tap_b(tap), c = tap_c(tap);
   const int grp = lane >> 4, cl = lane & 15;
-  const int rowlen = (g.n2 + 63) / 64;  // 64-cell segments per phi row
-  const long long nrows = (long long)g.n0 * g.n1 * rowlen;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (long long r = (long long)blockIdx.x * 4 + wv; r < nrows; r += (long long)gridDim.x * 4) {
-    const int seg = (int)(r % rowlen);
-    const long long ij = r / rowlen;
-    const int i = (int)(ij / g.n1), j = (int)(ij % g.n1);
-    const int ii = i + a, jj = j + b;
-    const bool rowok = ii >= 0 && ii < g.n0 && jj >= 0 && jj < g.n1;
+  const int ntk = (g.n2 + TKC - 1) / TKC, ntj = (g.n1 + TJC - 1) / TJC;
+  const long long n12 = (long long)g.n1 * g.n2;
+  f32x4 acc[NTAP + 1];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      bf16x8 av, bv;
+  for (int q = 0; q <= NTAP; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = seg * 64 + ks * 32 + grp * 8 + e;
-        const bool kin = k < g.n2;
-        const int kc = kin ? k : 0;
-        const __bf16 zero = (__bf16)0.0f;
-        av[e] = kin ? dout[(((long long)i * g.n1 + j) * g.n2 + kc) * CC + cl] : zero;
-        int ks2 = (kc + c) % g.n2;
-        if (ks2 < 0) ks2 += g.n2;
-        bv[e] = (kin && rowok) ? act[(((long long)ii * g.n1 + jj) * g.n2 + ks2) * CC + cl] : zero;
+  for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+  constexpr int NCH = PLC * 2;
+  constexpr int NLD = (NCH + 255) / 256;
+
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int bx = item % ntk, by = (item / ntk) % ntj, bz = item / (ntk * ntj);
+    const int k0 = bx * TKC, j0 = by * TJC;
+    const int i0 = bz * CI, i1 = min(i0 + CI, g.n0);
+    int src[NLD], dst[NLD];
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int ch = t + q * 256;
+      const int cell = ch >> 1, half = ch & 1;
+      const int hj = cell / HKC, hk = cell - hj * HKC;
+      const int jj = j0 - 1 + hj;
+      int kk = (k0 - 1 + hk) % g.n2;
+      if (kk < 0) kk += g.n2;
+      const bool ok = ch < NCH && jj >= 0 && jj < g.n1;
+      src[q] = ok ? ((jj * g.n2 + kk) * 2 + half) : -1;
+      dst[q] = ch < NCH ? lds_cell(cell) / 8 + half : -1;  // in uint4 units
+    }
+    // this thread's share of the dout tile: cell t, both halves
+    const int dj = t >> 6, dk = t & 63;
+    const bool din = j0 + dj < g.n1 && k0 + dk < g.n2;
+    const int doff = ((j0 + dj) * g.n2 + (k0 + dk)) * 2;
+    auto load_plane = [&](int ip, uint4 *v) {
+      const bool pin = ip >= 0 && ip < g.n0;
+      const uint4 *base = reinterpret_cast<const uint4 *>(act + (long long)(pin ? ip : 0) * n12 * CC);
+#pragma unroll
+      for (int q = 0; q < NLD; ++q) {
+        uint4 z = {0u, 0u, 0u, 0u};
+        v[q] = (pin && src[q] >= 0) ? base[src[q]] : z;
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    };
+    auto store_plane = [&](int ip, const uint4 *v) {
+      uint4 *sp = reinterpret_cast<uint4 *>(s_in[(ip + 3) % 3]);
+#pragma unroll
+      for (int q = 0; q < NLD; ++q)
+        if (dst[q] >= 0) sp[dst[q]] = v[q];
+    };
+    uint4 v[NLD];
+    __syncthreads();  // the previous item's reads of the ring are done
+    load_plane(i0 - 1, v);
+    store_plane(i0 - 1, v);
+    load_plane(i0, v);
+    store_plane(i0, v);
+    load_plane(i0 + 1, v);
+    store_plane(i0 + 1, v);
+    for (int i = i0; i < i1; ++i) {
+      const bool pre = i + 2 <= i1;
+      if (pre) load_plane(i + 2, v);
+      uint4 d0 = {0u, 0u, 0u, 0u}, d1 = {0u, 0u, 0u, 0u};
+      if (din) {
+        const uint4 *dp = reinterpret_cast<const uint4 *>(dout + (long long)i * n12 * CC);
+        d0 = dp[doff];
+        d1 = dp[doff + 1];
+      }
+      uint4 *sd = reinterpret_cast<uint4 *>(s_d);
+      sd[lds_cell(t) / 8] = d0;
+      sd[lds_cell(t) / 8 + 1] = d1;
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        bf16x8 av;
+        const int c0 = wv * TKC + ks * 32 + grp * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = s_d[lds_cell(c0 + e) + cl];
+        acc[NTAP] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, acc[NTAP], 0, 0, 0);
+#pragma unroll
+        for (int tap = 0; tap < NTAP; ++tap) {
+          const __bf16 *pl = s_in[(i + tap_a(tap) + 3) % 3];
+          const int h0 = (wv + 1 + tap_b(tap)) * HKC + 1 + tap_c(tap) + ks * 32 + grp * 8;
+          bf16x8 bv;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bv[e] = pl[lds_cell(h0 + e) + cl];
+          acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tap], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+      if (pre) store_plane(i + 2, v);
     }
   }
-  // C: lane holds co = 4 grp + e, ci = cl; sum the 4 wavefronts in fixed order
+  // sum the four wavefronts in a fixed order (ring memory reused)
+  __syncthreads();
+  float *red = reinterpret_cast<float *>(&s_in[0][0]);  // 4 x 256 floats per product
+  for (int q = 0; q <= NTAP; ++q) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) red[wv][(4 * grp + e) * 16 + cl] = acc[e];
-  __syncthreads();
-  const float s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-  part[((size_t)blockIdx.x * NTAP + tap) * 256 + t] = s;
-}
-
-// g[co][ci][tap] (the master-weight layout) = sum over workgroups of the
-// partials part[w][tap][co][ci], in workgroup order.
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, float *__restrict__ g) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (co * 16 + ci) * 27 + tap
-  if (idx >= NTAP * 256) return;
-  const int tap = idx % NTAP, cc = idx / NTAP;
-  float s = 0.f;
-  for (int w = 0; w < nwg; ++w) s += part[((size_t)w * NTAP + tap) * 256 + cc];
-  g[idx] = s;
-}
-
-// Bias gradient partials: sum_cells dout[cell][co]
-__global__ void __launch_bounds__(256)
-    k_bgrad(long long ncell, const __bf16 *__restrict__ dout, float *__restrict__ part) {
-  __shared__ float red[256];
-  const int t = threadIdx.x, co = t & 15;
-  float s = 0.f;
-  for (long long c = (long long)blockIdx.x * 16 + (t >> 4); c < ncell; c += (long long)gridDim.x * 16)
-    s += (float)dout[c * CC + co];
-  red[t] = s;
-  __syncthreads();
-  if (t < 16) {
-    float x = 0.f;
-    for (int q = 0; q < 16; ++q) x += red[q * 16 + t];
-    part[blockIdx.x * 16 + t] = x;
+    for (int e = 0; e < 4; ++e) red[wv * 256 + (4 * grp + e) * 16 + cl] = acc[q][e];
+    __syncthreads();
+    const float s4 = red[t] + red[256 + t] + red[512 + t] + red[768 + t];
+    part[((size_t)blockIdx.x * (NTAP + 1) + q) * 256 + t] = s4;
+    __syncthreads();
   }
 }
 
-__global__ void k_bgrad_reduce(const float *__restrict__ part, int nwg, float *__restrict__ db) {
-  const int co = threadIdx.x;
-  if (co >= 16) return;
+// g[co][ci][tap] (the master-weight layout) and g_bias[co] = sums over the
+// workgroups' partials part[w][q][co][ci], in workgroup order.
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, float *__restrict__ g) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= NTAP * 256 + CC) return;
+  size_t src;
+  if (idx < NTAP * 256) {
+    const int tap = idx % NTAP, cc = idx / NTAP;
+    src = (size_t)tap * 256 + cc;
+  } else {
+    src = (size_t)NTAP * 256 + (idx - NTAP * 256) * 16;  // bias: column ci = 0
+  }
+  const size_t stride = (size_t)(NTAP + 1) * 256;
   float s = 0.f;
-  for (int w = 0; w < nwg; ++w) s += part[w * 16 + co];
-  db[co] = s;
+  for (int w = 0; w < nwg; ++w) s += part[w * stride + src];
+  g[idx] = s;
 }
 
 // Network input: channel 0 = rhs * rs, channel 1 = (T - ts) * tsc, others 0.
@@ -389,22 +455,19 @@ void launch_cnn_conv(const CnnLaunch &L, int mode, const void *in, const void *w
   }
 }
 
-int cnn_wgrad_parts() { return 256; }
+int cnn_wgrad_parts() { return 512; }
 
-void launch_cnn_wgrad(const CnnLaunch &L, const void *act, const void *dout, float *part, float *g) {
+void launch_cnn_wgrad(const CnnLaunch &L, const void *act, const void *dout, float *part,
+                      float *g) {
   CnnGrid gr{L.n0, L.n1, L.n2};
-  const int nwg = cnn_wgrad_parts();
-  hipLaunchKernelGGL(k_wgrad, dim3(nwg, NTAP), dim3(256), 0, L.stream, gr, (const __bf16 *)act,
-                     (const __bf16 *)dout, part);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((NTAP * 256 + 255) / 256), dim3(256), 0, L.stream, part,
-                     nwg, g);
-}
-
-void launch_cnn_bgrad(const CnnLaunch &L, const void *dout, float *part, float *db) {
-  const int nwg = 256;
-  const long long n = (long long)L.n0 * L.n1 * L.n2;
-  hipLaunchKernelGGL(k_bgrad, dim3(nwg), dim3(256), 0, L.stream, n, (const __bf16 *)dout, part);
-  hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, L.stream, part, nwg, db);
+  const int ntk = (L.n2 + TKC - 1) / TKC, ntj = (L.n1 + TJC - 1) / TJC;
+  const int CI = conv_chunk(L.n0, ntk * ntj);
+  const int nitems = ntk * ntj * ((L.n0 + CI - 1) / CI);
+  const int nwg = std::min(nitems, cnn_wgrad_parts());
+  hipLaunchKernelGGL(k_wgrad, dim3(nwg), dim3(256), 0, L.stream, gr, (const __bf16 *)act,
+                     (const __bf16 *)dout, part, CI, nitems);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((NTAP * 256 + CC + 255) / 256), dim3(256), 0, L.stream,
+                     part, nwg, g);
 }
 
 void launch_cnn_pack_input(const CnnLaunch &L, const double *rhs, const double *T, double rs, double tsh,

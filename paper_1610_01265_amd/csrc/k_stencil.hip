@@ -32,6 +32,15 @@ namespace {
 #ifndef STS_MARCH_WG
 #define STS_MARCH_WG 2048
 #endif
+// STS_PF: per-cell operands loaded one plane ahead (1) or at their plane (0).
+// STS_HALO: the stencil-input plane staged into LDS at the end of iteration i
+// is loaded during iteration i (1) or during iteration i - 1 (2).
+#ifndef STS_PF
+#define STS_PF 0
+#endif
+#ifndef STS_HALO
+#define STS_HALO 2
+#endif
 constexpr int TK = 64, TJ = STS_MARCH_TJ, NT = TK * TJ;
 constexpr int HK = TK + 2, HJ = TJ + 2, PL = HK * HJ;  // one LDS plane (tile + halo)
 constexpr int NLOAD = (PL + NT - 1) / NT;
@@ -114,7 +123,6 @@ struct PlaneGeo {
   R s00m, s00, s10m, s10, s10p, s20m, s20, s20p, v0;
   R a00m, a00;  // isotropic: A00[i-1], A00[i]
   R a10, a20;   // isotropic: A10[i], A20[i]
-  int dIm;
 };
 
 template <class R>
@@ -142,31 +150,33 @@ __device__ __forceinline__ R edge_term_r(R K, R u00, R u10, R u01, R u11, const 
   return h * K * ((p ? -ya : ya) + (q ? -xb : xb));
 }
 
-// (S u)_c (+ g_c when WITH_G), u read through U(di, dj, dk); arithmetic in R,
-// coefficients stored as CT.
+// Coefficients of one cell's row of the conduction operator: its own +face
+// and edge coefficients and those of its -1 neighbours.  Edge order (p, q):
+// (0,0), (1,0), (0,1), (1,1) (p / q = 1: the edge's origin is one cell back
+// along the plane's first / second axis).
+template <class R>
+struct RowCoef {
+  R w0p, w0m, w1p, w1m, w2p, w2m;
+  R K01[4], K02[4], K12[4];
+};
+
+// (S u)_c (+ g_c when WITH_G), u read through U(di, dj, dk); arithmetic in R.
 template <int OP, bool WITH_G, class R, class CT, class UF>
-__device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const UF &U, int i, int j,
-                                     int k, int c, const PlaneGeo<R> &pg,
-                                     const ThreadGeo<R> &tg) {
+__device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const RowCoef<R> &W,
+                                     const UF &U, int i, int j, int k,
+                                     const PlaneGeo<R> &pg, const ThreadGeo<R> &tg) {
   const R u0 = U(0, 0, 0);
   const R zero = R(0);
   R acc;
   if (OP == OP_SPITZER) {
-    // unconditional coefficient loads (all indices lie inside the grid)
-    const int cA = c + pg.dIm, cB = c + tg.dJm, cC = c + tg.dKm;
-    const R w0p = C.w0[c], w0m = C.w0[cA], w1p = C.w1[c], w1m = C.w1[cB];
-    const R w2p = C.w2[c], w2m = C.w2[cC];
-    const R K01[4] = {R(C.k01[c]), R(C.k01[cA]), R(C.k01[cB]), R(C.k01[cA + tg.dJm])};
-    const R K02[4] = {R(C.k02[c]), R(C.k02[cA]), R(C.k02[cC]), R(C.k02[cA + tg.dKm])};
-    const R K12[4] = {R(C.k12[c]), R(C.k12[cB]), R(C.k12[cC]), R(C.k12[cB + tg.dKm])};
-    acc = w0p * (U(1, 0, 0) - u0) + (pg.A.hm ? w0m : zero) * (U(-1, 0, 0) - u0);
-    acc += w1p * (U(0, 1, 0) - u0) + (tg.B.hm ? w1m : zero) * (U(0, -1, 0) - u0);
-    acc += w2p * (U(0, 0, 1) - u0) + (tg.C.hm ? w2m : zero) * (U(0, 0, -1) - u0);
+    acc = W.w0p * (U(1, 0, 0) - u0) + (pg.A.hm ? W.w0m : zero) * (U(-1, 0, 0) - u0);
+    acc += W.w1p * (U(0, 1, 0) - u0) + (tg.B.hm ? W.w1m : zero) * (U(0, -1, 0) - u0);
+    acc += W.w2p * (U(0, 0, 1) - u0) + (tg.C.hm ? W.w2m : zero) * (U(0, 0, -1) - u0);
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int r = p + 2 * q;  // index into K**[]: (0,0), (1,0), (0,1), (1,1)
+        const int r = p + 2 * q;
         // plane (0, 1)
         {
           const bool ex = (p ? pg.A.hm : pg.A.hp) && (q ? tg.B.hm : tg.B.hp);
@@ -175,7 +185,7 @@ __device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const UF
           const R tj = q ? tg.t11m : tg.t11;
           e.ib0 = (p ? pg.s10m : pg.s10) * tj;
           e.ib1 = (p ? pg.s10 : pg.s10p) * tj;
-          acc += edge_term_r<R>(ex ? K01[r] : zero, U(-p, -q, 0), U(1 - p, -q, 0),
+          acc += edge_term_r<R>(ex ? W.K01[r] : zero, U(-p, -q, 0), U(1 - p, -q, 0),
                                 U(-p, 1 - q, 0), U(1 - p, 1 - q, 0), e, p, q);
         }
         // plane (0, 2)
@@ -186,7 +196,7 @@ __device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const UF
           const R tk = q ? tg.t22m : tg.t22;
           e.ib0 = (p ? pg.s20m : pg.s20) * tg.t21 * tk;
           e.ib1 = (p ? pg.s20 : pg.s20p) * tg.t21 * tk;
-          acc += edge_term_r<R>(ex ? K02[r] : zero, U(-p, 0, -q), U(1 - p, 0, -q),
+          acc += edge_term_r<R>(ex ? W.K02[r] : zero, U(-p, 0, -q), U(1 - p, 0, -q),
                                 U(-p, 0, 1 - q), U(1 - p, 0, 1 - q), e, p, q);
         }
         // plane (1, 2)
@@ -197,7 +207,7 @@ __device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const UF
           const R tk = q ? tg.t22m : tg.t22;
           e.ib0 = pg.s20 * (p ? tg.t21m : tg.t21) * tk;
           e.ib1 = pg.s20 * (p ? tg.t21 : tg.t21p) * tk;
-          acc += edge_term_r<R>(ex ? K12[r] : zero, U(0, -p, -q), U(0, 1 - p, -q),
+          acc += edge_term_r<R>(ex ? W.K12[r] : zero, U(0, -p, -q), U(0, 1 - p, -q),
                                 U(0, -p, 1 - q), U(0, 1 - p, 1 - q), e, p, q);
         }
       }
@@ -302,12 +312,72 @@ __global__ void __launch_bounds__(NT)
     tg.a22 = T2(g, T_A22, kc);
     tg.a22m = T2(g, T_A22, tg.C.m);
   }
+  // Per-plane loads of this thread, issued one plane ahead of their use:
+  // the conduction coefficients of the cell and of its (j-1), (k-1) and
+  // (j-1, k-1) neighbours in the same plane, and the consumer's operands.
+  // Coefficients of the previous plane are carried in registers.  Inactive
+  // threads load at their clamped cell, so every address is in the grid.
+  struct Loads {
+    R w0, w1, w2, k01, k02, k12;
+    R w1B, k01B, k12B, w2C, k02C, k12C, k12BC;
+    R x0, x2;   // RKL2: u_{k-2}, F0; FP32 stages: delta_{k-2}, F0
+    double x1;  // RKL2 / last FP32 stage: u_0; residuals: b
+  };
+  auto load_plane_cells = [&](int ip, Loads &L) {
+    const int c = (ip * g.n1 + jc) * g.n2 + kc;
+    if (OP == OP_SPITZER) {
+      const int cB = c + tg.dJm, cC = c + tg.dKm;
+      L.w0 = R(C.w0[c]);
+      L.w1 = R(C.w1[c]);
+      L.w2 = R(C.w2[c]);
+      L.k01 = R(C.k01[c]);
+      L.k02 = R(C.k02[c]);
+      L.k12 = R(C.k12[c]);
+      L.w1B = R(C.w1[cB]);
+      L.k01B = R(C.k01[cB]);
+      L.k12B = R(C.k12[cB]);
+      L.w2C = R(C.w2[cC]);
+      L.k02C = R(C.k02[cC]);
+      L.k12C = R(C.k12[cC]);
+      L.k12BC = R(C.k12[cB + tg.dKm]);
+    }
+    const long long cc = off + c;
+    if (MODE == M_RK || MODE == M_DK || MODE == M_DLAST) {
+      L.x0 = ((const R *)a.ukm2)[cc];
+      L.x2 = ((const R *)a.F0)[cc];
+    }
+    if (MODE == M_RK || MODE == M_DLAST) L.x1 = a.u0[cc];
+    if (MODE == M_RES || MODE == M_RESN) L.x1 = a.b[cc];
+  };
+  // coefficients of the previous plane (at the chunk start: loaded)
+  R pw0 = R(0), pk01 = R(0), pk02 = R(0), pk01B = R(0), pk02C = R(0);
+  if (OP == OP_SPITZER) {
+    const int cA = (nbr(i0, g.n0, g.per0).m * g.n1 + jc) * g.n2 + kc;
+    pw0 = R(C.w0[cA]);
+    pk01 = R(C.k01[cA]);
+    pk02 = R(C.k02[cA]);
+    pk01B = R(C.k01[cA + tg.dJm]);
+    pk02C = R(C.k02[cA + tg.dKm]);
+  }
+  Loads cur, nxt;
+  if (STS_PF) load_plane_cells(i0, cur);
+  R vn[NLOAD];  // STS_HALO == 2: plane i + 3 in flight
+  if (STS_HALO == 2 && i0 + 2 <= i1) load_plane(i0 + 2, v);
   double acc_a = 0.0, acc_b = 0.0;
   __syncthreads();
 
   for (int i = i0; i < i1; ++i) {
     const bool pre = i + 2 <= i1;
-    if (pre) load_plane(i + 2, v);
+    if (STS_HALO == 1) {
+      if (pre) load_plane(i + 2, v);
+    } else {
+      if (i + 3 <= i1) load_plane(i + 3, vn);
+    }
+    if (STS_PF) {
+      if (i + 1 < i1) load_plane_cells(i + 1, nxt);
+    } else {
+      load_plane_cells(i, cur);
+    }
     if (active) {
       PlaneGeo<R> pg;
       pg.A = nbr(i, g.n0, g.per0);
@@ -320,7 +390,6 @@ __global__ void __launch_bounds__(NT)
       pg.s20 = T0(g, T_IL20, i);
       pg.s20p = T0(g, T_IL20, pg.A.p);
       pg.v0 = T0(g, T_V0, i);
-      pg.dIm = (pg.A.m - i) * g.n1 * g.n2;
       if (OP == OP_ISOTROPIC) {
         pg.a00 = T0(g, T_A00, i);
         pg.a00m = T0(g, T_A00, pg.A.m);
@@ -333,10 +402,31 @@ __global__ void __launch_bounds__(NT)
         const R *s = di < 0 ? sm : (di > 0 ? sp : s0);
         return s[base + dj * HK + dk];
       };
+      RowCoef<R> W;
+      if (OP == OP_SPITZER) {
+        W.w0p = cur.w0;
+        W.w0m = pw0;
+        W.w1p = cur.w1;
+        W.w1m = cur.w1B;
+        W.w2p = cur.w2;
+        W.w2m = cur.w2C;
+        W.K01[0] = cur.k01;
+        W.K01[1] = pk01;
+        W.K01[2] = cur.k01B;
+        W.K01[3] = pk01B;
+        W.K02[0] = cur.k02;
+        W.K02[1] = pk02;
+        W.K02[2] = cur.k02C;
+        W.K02[3] = pk02C;
+        W.K12[0] = cur.k12;
+        W.K12[1] = cur.k12B;
+        W.K12[2] = cur.k12C;
+        W.K12[3] = cur.k12BC;
+      }
       const int c = (i * g.n1 + j) * g.n2 + k;
       const long long cc = off + c;
       constexpr bool with_g = MODE == M_F || MODE == M_RK1 || MODE == M_RK || MODE == M_F0F;
-      const R su = apply_S<OP, with_g, R, CT>(g, C, U, i, j, k, c, pg, tg);
+      const R su = apply_S<OP, with_g, R, CT>(g, C, W, U, i, j, k, pg, tg);
       const R V = pg.v0 * tg.v12;
       const R uc = s0[base];
       if (MODE == M_F) {
@@ -351,34 +441,44 @@ __global__ void __launch_bounds__(NT)
         ((R *)a.out)[cc] = uc + R(a.mut_dt) * F;
       } else if (MODE == M_RK) {
         const R F = su / V;
-        const R *ukm2 = (const R *)a.ukm2, *F0 = (const R *)a.F0;
-        ((R *)a.out)[cc] = R(a.mu) * uc + R(a.nu) * ukm2[cc] +
-                           (R(1) - R(a.mu) - R(a.nu)) * R(a.u0[cc]) + R(a.mut_dt) * F +
-                           R(a.gt_dt) * F0[cc];
+        ((R *)a.out)[cc] = R(a.mu) * uc + R(a.nu) * cur.x0 +
+                           (R(1) - R(a.mu) - R(a.nu)) * R(cur.x1) + R(a.mut_dt) * F +
+                           R(a.gt_dt) * cur.x2;
       } else if (MODE == M_DK || MODE == M_DLAST) {
         // delta_k = mu delta_{k-1} + nu delta_{k-2} + mu~ dt M delta_{k-1}
         //           + (mu~ + gamma~) dt F0      (gt_dt carries (mu~ + gamma~) dt)
-        const R *dkm2 = (const R *)a.ukm2, *F0 = (const R *)a.F0;
-        const R d = R(a.mu) * uc + R(a.nu) * dkm2[cc] + R(a.mut_dt) * (su / V) +
-                    R(a.gt_dt) * F0[cc];
+        const R d = R(a.mu) * uc + R(a.nu) * cur.x0 + R(a.mut_dt) * (su / V) +
+                    R(a.gt_dt) * cur.x2;
         if (MODE == M_DK)
           ((R *)a.out)[cc] = d;
         else
-          ((double *)a.out)[cc] = a.u0[cc] + (double)d;
+          ((double *)a.out)[cc] = cur.x1 + (double)d;
       } else if (MODE == M_PA) {
         const R yv = V * uc - R(a.dt) * su;
         ((R *)a.out)[cc] = uc;
         ((R *)a.y)[cc] = yv;
         acc_a += (double)uc * (double)yv;
       } else {  // residual r = b - A x
-        const double bv = a.b[cc];
+        const double bv = cur.x1;
         const double rv = bv - (double)(V * uc - R(a.dt) * su);
         if (MODE == M_RES) ((double *)a.out)[cc] = rv;
         acc_a += rv * rv;
         acc_b += bv * bv;
       }
     }
+    if (OP == OP_SPITZER) {
+      pw0 = cur.w0;
+      pk01 = cur.k01;
+      pk02 = cur.k02;
+      pk01B = cur.k01B;
+      pk02C = cur.k02C;
+    }
+    if (STS_PF) cur = nxt;
     if (pre) store_plane(i + 2, v);
+    if (STS_HALO == 2) {
+#pragma unroll
+      for (int q = 0; q < NLOAD; ++q) v[q] = vn[q];
+    }
     __syncthreads();
   }
   if (MODE == M_PA || MODE == M_RES || MODE == M_RESN)

@@ -26,6 +26,7 @@ namespace sts {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));  // 16-byte staging chunk
 
 namespace {
 
@@ -38,6 +39,16 @@ constexpr int PLC = HKC * HJC;   // cells per LDS plane (tile + halo)
 
 // epilogues of k_conv (numbers are the cnn_conv kinds of the C ABI)
 enum { CV_RELU = 0, CV_LAST = 1, CV_MASK = 2, CV_F32 = 3 };
+
+// target number of workgroups of the plane-marching kernels, and the output
+// planes the convolution computes per iteration (between two waits for
+// input planes; its LDS ring holds CNN_PPI + 2 planes)
+#ifndef CNN_WG_TARGET
+#define CNN_WG_TARGET 2048
+#endif
+#ifndef CNN_PPI
+#define CNN_PPI 1
+#endif
 
 struct CnnGrid {
   int n0, n1, n2;  // phi (axis 2) is circular; r, theta zero-padded
@@ -58,7 +69,8 @@ __global__ void __launch_bounds__(256)
     k_conv(CnnGrid g, const __bf16 *__restrict__ in, const __bf16 *__restrict__ wfrag,
            const float *__restrict__ bias, const __bf16 *__restrict__ mask,
            __bf16 *__restrict__ out_bf, float *__restrict__ outf, int CI, int nchunk) {
-  __shared__ __attribute__((aligned(16))) __bf16 s_in[3][PLC * CC];
+  constexpr int PP = CNN_PPI, RS = CNN_PPI + 2;  // planes per iteration, ring slots
+  __shared__ __attribute__((aligned(16))) __bf16 s_in[RS][PLC * CC];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int ntk = (g.n2 + TKC - 1) / TKC, ntj = (g.n1 + TJC - 1) / TJC;
   const int bx = blockIdx.x % ntk, by = (blockIdx.x / ntk) % ntj, bz = blockIdx.x / (ntk * ntj);
@@ -90,49 +102,49 @@ __global__ void __launch_bounds__(256)
     src[q] = ok ? ((jj * g.n2 + kk) * 2 + half) : -1;
     dst[q] = ch < NCH ? ch : -1;
   }
-  auto load_plane = [&](int ip, uint4 *v) {
+  auto load_plane = [&](int ip, u32x4 *v) {
     const bool pin = ip >= 0 && ip < g.n0;
-    const uint4 *base = reinterpret_cast<const uint4 *>(in + (long long)(pin ? ip : 0) * n12 * CC);
+    const u32x4 *base = reinterpret_cast<const u32x4 *>(in + (long long)(pin ? ip : 0) * n12 * CC);
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
-      uint4 z = {0u, 0u, 0u, 0u};
-      v[q] = (pin && src[q] >= 0) ? base[src[q]] : z;
+      v[q] = (pin && src[q] >= 0) ? base[src[q]] : u32x4(0u);
     }
   };
-  auto store_plane = [&](int ip, const uint4 *v) {
-    uint4 *s = reinterpret_cast<uint4 *>(s_in[(ip + 3) % 3]);
+  auto store_plane = [&](int ip, const u32x4 *v) {
+    u32x4 *s = reinterpret_cast<u32x4 *>(s_in[(ip + RS) % RS]);
 #pragma unroll
     for (int q = 0; q < NLD; ++q)
       if (dst[q] >= 0) s[dst[q]] = v[q];
   };
-  uint4 v[NLD];
-  load_plane(i0 - 1, v);
-  store_plane(i0 - 1, v);
-  load_plane(i0, v);
-  store_plane(i0, v);
-  load_plane(i0 + 1, v);
-  store_plane(i0 + 1, v);
+  u32x4 v[PP][NLD];
+  for (int ip = i0 - 1; ip <= i0 + PP; ++ip) {
+    load_plane(ip, v[0]);
+    store_plane(ip, v[0]);
+  }
   __syncthreads();
 
   const int grp = lane >> 4, cl = lane & 15;
   const int j = j0 + wv;
-  for (int i = i0; i < i1; ++i) {
-    const bool pre = i + 2 <= i1;
-    if (pre) load_plane(i + 2, v);
+  // output plane i from input planes i-1, i, i+1 of the ring
+  auto compute = [&](int i) {
     f32x4 acc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < NSTEP; ++s) {
+    auto load_b = [&](int s, bf16x8 *bv) {
       const int tap = min(2 * s + (grp >> 1), NTAP - 1);  // tap 27 has zero weights
       const int a = tap_a(tap), b = tap_b(tap), c = tap_c(tap);
-      const bf16x8 *pl = reinterpret_cast<const bf16x8 *>(s_in[(i + a + 3) % 3]);
+      const bf16x8 *pl = reinterpret_cast<const bf16x8 *>(s_in[(i + a + RS) % RS]);
       const int rowb = (wv + 1 + b) * HKC + 1 + c + cl;
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const bf16x8 bv = pl[(rowb + 16 * nb) * 2 + (grp & 1)];
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc[nb], 0, 0, 0);
-      }
+      for (int nb = 0; nb < 4; ++nb) bv[nb] = pl[(rowb + 16 * nb) * 2 + (grp & 1)];
+    };
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+      bf16x8 bv[4];
+      load_b(s, bv);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv[nb], acc[nb], 0, 0, 0);
     }
     if (j < g.n1) {
 #pragma unroll
@@ -167,8 +179,21 @@ __global__ void __launch_bounds__(256)
         }
       }
     }
+  };
+  // each iteration: outputs i .. i+PP-1 (inputs i-1 .. i+PP in the ring),
+  // meanwhile the inputs of the next iteration, i+PP+1 .. i+2PP, are loaded
+  // into registers and staged over the planes i-1 .. i+PP-2 afterwards
+  for (int i = i0; i < i1; i += PP) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q)
+      if (i + PP + 1 + q <= i1) load_plane(i + PP + 1 + q, v[q]);
+#pragma unroll
+    for (int q = 0; q < PP; ++q)
+      if (i + q < i1) compute(i + q);
     __syncthreads();
-    if (pre) store_plane(i + 2, v);
+#pragma unroll
+    for (int q = 0; q < PP; ++q)
+      if (i + PP + 1 + q <= i1) store_plane(i + PP + 1 + q, v[q]);
     __syncthreads();
   }
 }
@@ -223,28 +248,27 @@ __global__ void __launch_bounds__(256)
       if (kk < 0) kk += g.n2;
       const bool ok = ch < NCH && jj >= 0 && jj < g.n1;
       src[q] = ok ? ((jj * g.n2 + kk) * 2 + half) : -1;
-      dst[q] = ch < NCH ? lds_cell(cell) / 8 + half : -1;  // in uint4 units
+      dst[q] = ch < NCH ? lds_cell(cell) / 8 + half : -1;  // in 16-byte units
     }
     // this thread's share of the dout tile: cell t, both halves
     const int dj = t >> 6, dk = t & 63;
     const bool din = j0 + dj < g.n1 && k0 + dk < g.n2;
     const int doff = ((j0 + dj) * g.n2 + (k0 + dk)) * 2;
-    auto load_plane = [&](int ip, uint4 *v) {
+    auto load_plane = [&](int ip, u32x4 *v) {
       const bool pin = ip >= 0 && ip < g.n0;
-      const uint4 *base = reinterpret_cast<const uint4 *>(act + (long long)(pin ? ip : 0) * n12 * CC);
+      const u32x4 *base = reinterpret_cast<const u32x4 *>(act + (long long)(pin ? ip : 0) * n12 * CC);
 #pragma unroll
       for (int q = 0; q < NLD; ++q) {
-        uint4 z = {0u, 0u, 0u, 0u};
-        v[q] = (pin && src[q] >= 0) ? base[src[q]] : z;
+        v[q] = (pin && src[q] >= 0) ? base[src[q]] : u32x4(0u);
       }
     };
-    auto store_plane = [&](int ip, const uint4 *v) {
-      uint4 *sp = reinterpret_cast<uint4 *>(s_in[(ip + 3) % 3]);
+    auto store_plane = [&](int ip, const u32x4 *v) {
+      u32x4 *sp = reinterpret_cast<u32x4 *>(s_in[(ip + 3) % 3]);
 #pragma unroll
       for (int q = 0; q < NLD; ++q)
         if (dst[q] >= 0) sp[dst[q]] = v[q];
     };
-    uint4 v[NLD];
+    u32x4 v[NLD];
     __syncthreads();  // the previous item's reads of the ring are done
     load_plane(i0 - 1, v);
     store_plane(i0 - 1, v);
@@ -255,13 +279,13 @@ __global__ void __launch_bounds__(256)
     for (int i = i0; i < i1; ++i) {
       const bool pre = i + 2 <= i1;
       if (pre) load_plane(i + 2, v);
-      uint4 d0 = {0u, 0u, 0u, 0u}, d1 = {0u, 0u, 0u, 0u};
+      u32x4 d0 = u32x4(0u), d1 = u32x4(0u);
       if (din) {
-        const uint4 *dp = reinterpret_cast<const uint4 *>(dout + (long long)i * n12 * CC);
+        const u32x4 *dp = reinterpret_cast<const u32x4 *>(dout + (long long)i * n12 * CC);
         d0 = dp[doff];
         d1 = dp[doff + 1];
       }
-      uint4 *sd = reinterpret_cast<uint4 *>(s_d);
+      u32x4 *sd = reinterpret_cast<u32x4 *>(s_d);
       sd[lds_cell(t) / 8] = d0;
       sd[lds_cell(t) / 8 + 1] = d1;
       __syncthreads();
@@ -422,7 +446,7 @@ __global__ void __launch_bounds__(256)
 }
 
 int conv_chunk(int n0, int ntiles) {
-  long long ci = (long long)ntiles * n0 / 1024;
+  long long ci = (long long)ntiles * n0 / CNN_WG_TARGET;
   if (ci < 1) ci = 1;
   if (ci > 16) ci = 16;
   return (int)ci;

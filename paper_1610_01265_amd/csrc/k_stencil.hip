@@ -32,7 +32,8 @@ namespace {
 #ifndef STS_MARCH_WG
 #define STS_MARCH_WG 2048
 #endif
-// STS_PF: per-cell operands loaded one plane ahead (1) or at their plane (0).
+// STS_PF: per-cell operands loaded one plane ahead (1), only the cell's own
+// streams one plane ahead (2), or all at their plane (0).
 // STS_HALO: the stencil-input plane staged into LDS at the end of iteration i
 // is loaded during iteration i (1) or during iteration i - 1 (2).
 #ifndef STS_PF
@@ -238,8 +239,11 @@ __device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const Ro
   return acc;
 }
 
+#ifndef STS_MARCH_WPE
+#define STS_MARCH_WPE 1
+#endif
 template <int OP, int MODE, class Loader, class CT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     k_march(Grid g, CoefS<CT> C, Loader ld, Args a, int CI, int nchunk, long long ncell) {
   using R = typename Loader::value_type;
   if (MODE == M_PA && a.sc->done) return;
@@ -323,23 +327,16 @@ __global__ void __launch_bounds__(NT)
     R x0, x2;   // RKL2: u_{k-2}, F0; FP32 stages: delta_{k-2}, F0
     double x1;  // RKL2 / last FP32 stage: u_0; residuals: b
   };
-  auto load_plane_cells = [&](int ip, Loads &L) {
+  // own-cell streams (HBM) of plane ip
+  auto load_own = [&](int ip, Loads &L) {
     const int c = (ip * g.n1 + jc) * g.n2 + kc;
     if (OP == OP_SPITZER) {
-      const int cB = c + tg.dJm, cC = c + tg.dKm;
       L.w0 = R(C.w0[c]);
       L.w1 = R(C.w1[c]);
       L.w2 = R(C.w2[c]);
       L.k01 = R(C.k01[c]);
       L.k02 = R(C.k02[c]);
       L.k12 = R(C.k12[c]);
-      L.w1B = R(C.w1[cB]);
-      L.k01B = R(C.k01[cB]);
-      L.k12B = R(C.k12[cB]);
-      L.w2C = R(C.w2[cC]);
-      L.k02C = R(C.k02[cC]);
-      L.k12C = R(C.k12[cC]);
-      L.k12BC = R(C.k12[cB + tg.dKm]);
     }
     const long long cc = off + c;
     if (MODE == M_RK || MODE == M_DK || MODE == M_DLAST) {
@@ -348,6 +345,25 @@ __global__ void __launch_bounds__(NT)
     }
     if (MODE == M_RK || MODE == M_DLAST) L.x1 = a.u0[cc];
     if (MODE == M_RES || MODE == M_RESN) L.x1 = a.b[cc];
+  };
+  // same-plane neighbour coefficients of plane ip (loaded by neighbouring
+  // threads as their own: cache hits)
+  auto load_nbr = [&](int ip, Loads &L) {
+    if (OP == OP_SPITZER) {
+      const int c = (ip * g.n1 + jc) * g.n2 + kc;
+      const int cB = c + tg.dJm, cC = c + tg.dKm;
+      L.w1B = R(C.w1[cB]);
+      L.k01B = R(C.k01[cB]);
+      L.k12B = R(C.k12[cB]);
+      L.w2C = R(C.w2[cC]);
+      L.k02C = R(C.k02[cC]);
+      L.k12C = R(C.k12[cC]);
+      L.k12BC = R(C.k12[cB + tg.dKm]);
+    }
+  };
+  auto load_plane_cells = [&](int ip, Loads &L) {
+    load_own(ip, L);
+    load_nbr(ip, L);
   };
   // coefficients of the previous plane (at the chunk start: loaded)
   R pw0 = R(0), pk01 = R(0), pk02 = R(0), pk01B = R(0), pk02C = R(0);
@@ -360,7 +376,8 @@ __global__ void __launch_bounds__(NT)
     pk02C = R(C.k02[cA + tg.dKm]);
   }
   Loads cur, nxt;
-  if (STS_PF) load_plane_cells(i0, cur);
+  if (STS_PF == 1) load_plane_cells(i0, cur);
+  if (STS_PF == 2) load_own(i0, cur);
   R vn[NLOAD];  // STS_HALO == 2: plane i + 3 in flight
   if (STS_HALO == 2 && i0 + 2 <= i1) load_plane(i0 + 2, v);
   double acc_a = 0.0, acc_b = 0.0;
@@ -373,8 +390,11 @@ __global__ void __launch_bounds__(NT)
     } else {
       if (i + 3 <= i1) load_plane(i + 3, vn);
     }
-    if (STS_PF) {
+    if (STS_PF == 1) {
       if (i + 1 < i1) load_plane_cells(i + 1, nxt);
+    } else if (STS_PF == 2) {
+      load_nbr(i, cur);
+      if (i + 1 < i1) load_own(i + 1, nxt);
     } else {
       load_plane_cells(i, cur);
     }
@@ -473,7 +493,7 @@ __global__ void __launch_bounds__(NT)
       pk01B = cur.k01B;
       pk02C = cur.k02C;
     }
-    if (STS_PF) cur = nxt;
+    if (STS_PF) cur = nxt;  // (neighbour values of cur are reloaded at their plane)
     if (pre) store_plane(i + 2, v);
     if (STS_HALO == 2) {
 #pragma unroll

@@ -190,3 +190,32 @@ def run(shape=(128, 128, 256), train_seeds=range(200), test_seeds=range(200, 250
     s = summary(results)
     s["loss_per_epoch"] = hist
     return s, results, t, net, prob
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="learned initial guess: train on seeded BE solves, "
+                                             "compare Jacobi-PCG from zero / previous / network")
+    ap.add_argument("--shape", type=int, nargs=3, default=(128, 128, 256))
+    ap.add_argument("--train", type=int, nargs=2, default=(0, 200), help="seed range [a, b)")
+    ap.add_argument("--test", type=int, nargs=2, default=(200, 250), help="seed range [a, b)")
+    ap.add_argument("--ratio", type=float, default=200.0, help="dt / dt_Euler")
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--workers", type=int, default=8)
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    s, results, t, net, prob = run(tuple(a.shape), range(*a.train), range(*a.test), a.ratio,
+                                   a.epochs, a.lr, rtol=a.rtol, workers=a.workers,
+                                   log=lambda m: print(m, flush=True))
+    s.update(t)
+    s["per_seed_iters"] = {r.seed: r.iters for r in results}
+    print(json.dumps(s), flush=True)
+    net.close()
+    prob.ctx.close()
+
+
+if __name__ == "__main__":
+    main()

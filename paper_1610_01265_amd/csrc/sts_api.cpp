@@ -115,6 +115,11 @@ int stage_count(double ratio) {
 
 constexpr int kMaxStages = 1 << 20;
 constexpr int kPollEvery = 8;  // PCG iterations enqueued between host polls
+#ifndef STS_RK_FUSE
+#define STS_RK_FUSE 0
+#endif
+constexpr bool kRkFuse = STS_RK_FUSE;         // two stages per sweep where possible
+constexpr int kRkBuffers = kRkFuse ? 4 : 2;  // RKL2 state buffers besides F0
 
 }  // namespace
 
@@ -499,31 +504,64 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
   if (ctx->rk_ncomp < ncomp) {
     dfree(ctx->d_rk);
     ctx->rk_ncomp = 0;
-    sts_status st = dalloc(ctx, (void **)&ctx->d_rk, (size_t)3 * n * 8);
+    sts_status st = dalloc(ctx, (void **)&ctx->d_rk, (size_t)(1 + kRkBuffers) * n * 8);
     if (st) return st;
     ctx->rk_ncomp = ncomp;
   }
-  double *F0 = ctx->d_rk, *Ya = ctx->d_rk + n, *Yb = ctx->d_rk + 2 * n;
+  double *F0 = ctx->d_rk;
+  double *P[kRkBuffers];
+  for (int q = 0; q < kRkBuffers; ++q) P[q] = ctx->d_rk + (1 + q) * n;
   // stage coefficients (Sec. 3): b_k, mu_k, nu_k, mu~_k, gamma~_k
   const double ss = (double)s * s + s - 2.0;
   auto bk = [](int k) { return k <= 2 ? 1.0 / 3.0 : ((double)k * k + k - 2.0) / (2.0 * k * (k + 1.0)); };
-  const double w1 = 4.0 / ss;
-  launch_stage(ctx, 1, ncomp, u, nullptr, u, F0, Ya, 0, 0, (w1 / 3.0) * dt, 0);
-  LAUNCHCHK();
-  for (int k = 2; k <= s; ++k) {
+  auto coef = [&](int k, double out[4]) {
     const double b = bk(k), b1 = bk(k - 1), b2 = bk(k - 2);
-    const double mu = (2.0 * k - 1.0) / k * b / b1;
-    const double nu = -(k - 1.0) / k * b / b2;
     const double mut = 4.0 * (2.0 * k - 1.0) / (k * ss) * b / b1;
-    const double gt = -(1.0 - b1) * mut;
-    const double *ukm1 = ((k - 1) & 1) ? Ya : Yb;
-    const double *ukm2 = (k == 2) ? u : (((k - 2) & 1) ? Ya : Yb);
-    double *out = (k == s) ? u : ((k & 1) ? Ya : Yb);
-    launch_stage(ctx, 2, ncomp, ukm1, ukm2, u, F0, out, mu, nu, mut * dt, gt * dt);
-    LAUNCHCHK();
+    out[0] = (2.0 * k - 1.0) / k * b / b1;  // mu_k
+    out[1] = -(k - 1.0) / k * b / b2;       // nu_k
+    out[2] = mut * dt;                      // mu~_k dt
+    out[3] = -(1.0 - b1) * mut * dt;        // gamma~_k dt
+  };
+  const double w1 = 4.0 / ss;
+  launch_stage(ctx, 1, ncomp, u, nullptr, u, F0, P[0], 0, 0, (w1 / 3.0) * dt, 0);
+  LAUNCHCHK();
+  // u_{k-1} in prev1, u_{k-2} in prev2 (u_0 = u for k = 2).  Pairs of stages
+  // write into buffers that hold neither input; a single stage overwrites
+  // u_{k-2}, and the last stage writes u in place (it reads u_0 only at its
+  // own cell).
+  const double *prev1 = P[0], *prev2 = u;
+  auto free_buf = [&](const double *x, const double *y, const double *z) {
+    for (int q = 0; q < kRkBuffers; ++q)
+      if (P[q] != x && P[q] != y && P[q] != z) return P[q];
+    return (double *)nullptr;
+  };
+  int k = 2;
+  while (k <= s) {
+    double c1[4];
+    coef(k, c1);
+    if (kRkFuse && k + 1 < s) {
+      double c2[4];
+      coef(k + 1, c2);
+      double *o1 = free_buf(prev1, prev2, nullptr);
+      double *o2 = free_buf(prev1, prev2, o1);
+      launch_stage2(ctx, ncomp, prev1, prev2, u, F0, o1, o2, c1, c2);
+      LAUNCHCHK();
+      prev2 = o1;
+      prev1 = o2;
+      k += 2;
+    } else {
+      // a single stage reads u_{k-2} only at its own cell: it may overwrite it
+      double *out = (k == s) ? u : (prev2 != u ? (double *)prev2 : free_buf(prev1, prev2, nullptr));
+      launch_stage(ctx, 2, ncomp, prev1, prev2, u, F0, out, c1[0], c1[1], c1[2], c1[3]);
+      LAUNCHCHK();
+      prev2 = prev1;
+      prev1 = out;
+      k += 1;
+    }
   }
   return STS_OK;
 }
+
 
 static sts_status pcg_workspace(sts_ctx *ctx, int pc, const int block[3], double **fac) {
   const long long n = ctx->ncell;

@@ -90,7 +90,7 @@ struct sts_ctx {
   double dt_euler = -1.0;     // cached Gershgorin limit (< 0: not computed)
 
   // workspace
-  double *d_rk = nullptr;     // RKL2: F0, Ya, Yb (3 * ncell * ncomp_cap)
+  double *d_rk = nullptr;     // RKL2: F0 and 2 (4 with fused stages) state buffers
   int rk_ncomp = 0;
   float *d_rk32 = nullptr;    // FP32 form RKL2: F0, delta_a, delta_b
   int rk32_ncomp = 0;
@@ -130,6 +130,12 @@ int gershgorin_parts(const sts_ctx *c);
 void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, const double *ukm2,
                   const double *u0, double *F0, double *out, double mu, double nu, double mut_dt,
                   double gt_dt);
+
+// two RKL2 stages k, k+1 in one sweep: out1 = u_k, out2 = u_{k+1} (neither
+// may alias an input); st = {mu, nu, mu~ dt, gamma~ dt} of each stage
+void launch_stage2(const sts_ctx *c, int ncomp, const double *ukm1, const double *ukm2,
+                   const double *u0, const double *F0, double *out1, double *out2,
+                   const double st1[4], const double st2[4]);
 
 // FP32 form (k_stencil.hip, k_pcg.hip)
 void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1, double mut_dt);

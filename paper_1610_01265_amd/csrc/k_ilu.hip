@@ -226,53 +226,59 @@ __global__ void __launch_bounds__(ATH)
     }
   }
   __syncthreads();
-  const int li = t >> 3, lj = t & 7;
-  const bool col = t < 64 && li < e0 && lj < e1;
-  const int nlev = 3 * (e0 - 1) + 2 * (e1 - 1) + (e2 - 1) + 1;
-  // Both sweeps are branch-free: L entries of neighbours outside the block
-  // are stored as zero, so a neighbour index only has to stay inside the
-  // LDS arrays (clamped); the 18 LDS reads of a row can then all be issued
-  // before the multiply-add chain.
-  int loff[9];
+  // Both sweeps run on wavefront 0 alone: a level's rows read z values
+  // written at earlier levels by other lanes of the same wavefront, and the
+  // LDS operations of one wavefront complete in issue order, so a wave-level
+  // compiler barrier (no instruction) between levels is the only ordering
+  // needed.  The sweeps are branch-free: L entries of neighbours outside the
+  // block are stored as zero, so a neighbour index only has to stay inside
+  // the LDS arrays (clamped); the 18 LDS reads of a row are issued before a
+  // pairwise sum of the 9 products.
+  if (t < 64) {
+    const int li = t >> 3, lj = t & 7;
+    const bool col = li < e0 && lj < e1;
+    const int nlev = 3 * (e0 - 1) + 2 * (e1 - 1) + (e2 - 1) + 1;
+    int loff[9];
 #pragma unroll
-  for (int s = 0; s < 9; ++s) loff[s] = (c_off[s][0] * B1 + c_off[s][1]) * B2 + c_off[s][2];
-  // forward: z*_i = r_i - sum_k L_ik z*_k
-  for (int lev = 0; lev < nlev; ++lev) {
-    const int lk = lev - 3 * li - 2 * lj;
-    if (col && lk >= 0 && lk < e2) {
-      const int l = (li * B1 + lj) * B2 + lk;
-      double lv[9], zv[9];
+    for (int s = 0; s < 9; ++s) loff[s] = (c_off[s][0] * B1 + c_off[s][1]) * B2 + c_off[s][2];
+    auto sum9 = [](const double *lv, const double *zv) {
+      const double a = lv[0] * zv[0] + lv[1] * zv[1], b = lv[2] * zv[2] + lv[3] * zv[3];
+      const double c = lv[4] * zv[4] + lv[5] * zv[5], d = lv[6] * zv[6] + lv[7] * zv[7];
+      return ((a + b) + (c + d)) + lv[8] * zv[8];
+    };
+    // forward: z*_i = r_i - sum_k L_ik z*_k
+    for (int lev = 0; lev < nlev; ++lev) {
+      const int lk = lev - 3 * li - 2 * lj;
+      if (col && lk >= 0 && lk < e2) {
+        const int l = (li * B1 + lj) * B2 + lk;
+        double lv[9], zv[9];
 #pragma unroll
-      for (int s = 0; s < 9; ++s) {
-        lv[s] = sL[s][l];
-        zv[s] = sz[min(max(l + loff[s], 0), BS - 1)];
+        for (int s = 0; s < 9; ++s) {
+          lv[s] = sL[s][l];
+          zv[s] = sz[min(max(l + loff[s], 0), BS - 1)];
+        }
+        sz[l] = sz[l] - sum9(lv, zv);
       }
-      double acc = sz[l];
-#pragma unroll
-      for (int s = 0; s < 9; ++s) acc -= lv[s] * zv[s];
-      sz[l] = acc;
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-  }
-  // backward: z_i = z*_i / D_i - sum_j L_ji z_j over upper neighbours j
-  for (int lev = nlev - 1; lev >= 0; --lev) {
-    const int lk = lev - 3 * li - 2 * lj;
-    if (col && lk >= 0 && lk < e2) {
-      const int l = (li * B1 + lj) * B2 + lk;
-      double lv[9], zv[9];
+    // backward: z_i = z*_i / D_i - sum_j L_ji z_j over upper neighbours j
+    for (int lev = nlev - 1; lev >= 0; --lev) {
+      const int lk = lev - 3 * li - 2 * lj;
+      if (col && lk >= 0 && lk < e2) {
+        const int l = (li * B1 + lj) * B2 + lk;
+        double lv[9], zv[9];
 #pragma unroll
-      for (int s = 0; s < 9; ++s) {
-        const int j = min(max(l - loff[s], 0), BS - 1);
-        lv[s] = (l - loff[s] == j) ? sL[s][j] : 0.0;
-        zv[s] = sz[j];
+        for (int s = 0; s < 9; ++s) {
+          const int j = min(max(l - loff[s], 0), BS - 1);
+          lv[s] = (l - loff[s] == j) ? sL[s][j] : 0.0;
+          zv[s] = sz[j];
+        }
+        sz[l] = sz[l] * sI[l] - sum9(lv, zv);
       }
-      double acc = sz[l] * sI[l];
-#pragma unroll
-      for (int s = 0; s < 9; ++s) acc -= lv[s] * zv[s];
-      sz[l] = acc;
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
   }
+  __syncthreads();
   double rz = 0.0, rr = 0.0;
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
@@ -282,6 +288,141 @@ __global__ void __launch_bounds__(ATH)
       z[cidx[m]] = zv;
       rz += sr[l] * zv;
       rr += sr[l] * sr[l];
+    }
+  }
+  if (part) wg_sum2<ATH>(rz, rr, t, part + bid, part + cap + bid);
+}
+
+// The same apply for 8 x 8 x 8 blocks with compile-time neighbour offsets.
+// Every neighbour read is an immediate-offset LDS load off the row's own
+// address: z has a zero pad of PADZ entries before and after the block and
+// each L row a zero pad of PADZ after it, so no index needs clamping, and an
+// upper-neighbour coupling L_ji is read as stored (the factorisation stores
+// zero for couplings that leave the block, which covers the pads' role).
+// Edge blocks (fewer than 8 cells along an axis) are handled as full 8^3
+// blocks whose missing cells have L = 0, 1/D = 1 and r = 0.
+constexpr int B8 = 8, BS8 = 512;
+constexpr int PADZ = (B8 + 1) * B8 + 1;  // largest |offset| of a lower neighbour
+constexpr int LROW = BS8 + PADZ;
+template <bool UPDATE>
+__global__ void __launch_bounds__(ATH)
+    k_ilu_apply8(Grid g, BlockGeo bg, const double *__restrict__ fac, double *__restrict__ x,
+                 const double *__restrict__ p, double *__restrict__ r,
+                 const double *__restrict__ y, double *__restrict__ z, double *part,
+                 long long cap, const PcgScalars *sc) {
+  if (UPDATE && sc->done) return;
+  __shared__ double sL[9 * LROW];
+  __shared__ double sI[BS8];
+  __shared__ double szp[PADZ + BS8 + PADZ];
+  double *sz = szp + PADZ;
+  const int bid = blockIdx.x, t = threadIdx.x;
+  int o0, o1, o2, e0, e1, e2;
+  bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
+  const double *fb = fac + (size_t)bid * 10 * BS8;
+  const double alpha = UPDATE ? sc->alpha : 0.0;
+  constexpr int PER = BS8 / ATH;
+  // factors -> LDS, pads -> 0
+#pragma unroll
+  for (int s = 0; s < 10; ++s) {
+    double v[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) v[m] = fb[s * BS8 + t + ATH * m];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      if (s < 9)
+        sL[s * LROW + t + ATH * m] = v[m];
+      else
+        sI[t + ATH * m] = v[m];
+    }
+  }
+  for (int q = t; q < 9 * PADZ; q += ATH) sL[(q / PADZ) * LROW + BS8 + q % PADZ] = 0.0;
+  for (int q = t; q < PADZ; q += ATH) {
+    szp[q] = 0.0;
+    szp[PADZ + BS8 + q] = 0.0;
+  }
+  // x, r updates; r -> LDS (missing cells of edge blocks: 0)
+  int cidx[PER];
+  bool cval[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int l = t + ATH * m;
+    const int li = l >> 6, lj = (l >> 3) & 7, lk = l & 7;
+    cval[m] = li < e0 && lj < e1 && lk < e2;
+    cidx[m] = lin(g, o0 + min(li, e0 - 1), o1 + min(lj, e1 - 1), o2 + min(lk, e2 - 1));
+  }
+  double rl[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int c = cidx[m];
+    if (UPDATE) {
+      const double xv = x[c], pv = p[c], rv = r[c], yv = y[c];
+      rl[m] = cval[m] ? rv - alpha * yv : 0.0;
+      if (cval[m]) {
+        x[c] = xv + alpha * pv;
+        r[c] = rl[m];
+      }
+    } else {
+      const double rv = r[c];
+      rl[m] = cval[m] ? rv : 0.0;
+    }
+    sz[t + ATH * m] = rl[m];
+  }
+  __syncthreads();
+  // lower-neighbour offsets (ascending lexicographic order, as c_off)
+  constexpr int LO[9] = {-72, -65, -64, -63, -56, -9, -8, -7, -1};
+  if (t < 64) {
+    const int li = t >> 3, lj = t & 7;
+    const int d = 3 * li + 2 * lj;
+    constexpr int NLEV = 3 * 7 + 2 * 7 + 7 + 1;
+    auto sum9 = [](const double *lv, const double *zv) {
+      const double a = lv[0] * zv[0] + lv[1] * zv[1], b = lv[2] * zv[2] + lv[3] * zv[3];
+      const double c = lv[4] * zv[4] + lv[5] * zv[5], e = lv[6] * zv[6] + lv[7] * zv[7];
+      return ((a + b) + (c + e)) + lv[8] * zv[8];
+    };
+    // forward: z*_i = r_i - sum_k L_ik z*_k
+    for (int lev = 0; lev < NLEV; ++lev) {
+      const int lk = lev - d;
+      if (lk >= 0 && lk < B8) {
+        const int l = t * B8 + lk;
+        const double *zr = sz + l;
+        const double *lr = sL + l;
+        double lv[9], zv[9];
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+          lv[s] = lr[s * LROW];
+          zv[s] = zr[LO[s]];
+        }
+        sz[l] = zr[0] - sum9(lv, zv);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    // backward: z_i = z*_i / D_i - sum_j L_ji z_j over upper neighbours j = i - LO[s]
+    for (int lev = NLEV - 1; lev >= 0; --lev) {
+      const int lk = lev - d;
+      if (lk >= 0 && lk < B8) {
+        const int l = t * B8 + lk;
+        const double *zr = sz + l;
+        double lv[9], zv[9];
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+          lv[s] = sL[s * LROW + l - LO[s]];
+          zv[s] = zr[-LO[s]];
+        }
+        sz[l] = zr[0] * sI[l] - sum9(lv, zv);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  double rz = 0.0, rr = 0.0;
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int l = t + ATH * m;
+    if (cval[m]) {
+      const double zv = sz[l];
+      z[cidx[m]] = zv;
+      rz += rl[m] * zv;
+      rr += rl[m] * rl[m];
     }
   }
   if (part) wg_sum2<ATH>(rz, rr, t, part + bid, part + cap + bid);
@@ -316,9 +457,18 @@ void launch_ilu_factor(const sts_ctx *c, double dt, const int block[3], double *
                        c->coef(), dt, block_geo(c, block), fac, bad);
 }
 
+bool is8(const int block[3]) { return block[0] == 8 && block[1] == 8 && block[2] == 8; }
+
 void launch_ilu_apply_init(const sts_ctx *c, const int block[3], const double *fac,
                            const double *r, double *z) {
   const int nb = ilu_nblocks(c, block);
+  if (is8(block)) {
+    hipLaunchKernelGGL(k_ilu_apply8<false>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
+                       block_geo(c, block), fac, (double *)nullptr, (const double *)nullptr,
+                       const_cast<double *>(r), (const double *)nullptr, z, (double *)nullptr,
+                       0LL, (const PcgScalars *)nullptr);
+    return;
+  }
   hipLaunchKernelGGL(k_ilu_apply<false>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
                      block_geo(c, block), fac, (double *)nullptr, (const double *)nullptr,
                      const_cast<double *>(r), (const double *)nullptr, z, (double *)nullptr, 0LL,
@@ -329,6 +479,11 @@ void launch_pass_b_ilu(const sts_ctx *c, const int block[3], const double *fac, 
                        const double *p, double *r, const double *y, double *z, double *part,
                        const PcgScalars *sc) {
   const int nb = ilu_nblocks(c, block);
+  if (is8(block)) {
+    hipLaunchKernelGGL(k_ilu_apply8<true>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
+                       block_geo(c, block), fac, x, p, r, y, z, part, (long long)c->red_cap, sc);
+    return;
+  }
   hipLaunchKernelGGL(k_ilu_apply<true>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
                      block_geo(c, block), fac, x, p, r, y, z, part, (long long)c->red_cap, sc);
 }

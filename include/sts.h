@@ -124,6 +124,23 @@ sts_status apply_F(sts_ctx *ctx, const double *u, double *Fu, int ncomp);
  * receives s.  Each stage is one fused stencil + recurrence kernel.  */
 sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used);
 
+/* rkl_step - the super-step with the variants discussed in Sec. 6 (with
+ * Fig. "ampfac") and after Eq. rkl2_s, in this order:
+ *   euler_fraction in [0, 1): first advance euler_fraction * dt by explicit
+ *     Euler sub-steps u += h F(u) of equal length h <= euler_cfl * dt_E
+ *     (euler_cfl in (0, 1]; ignored when euler_fraction = 0);
+ *   then nsub (>= 1) sub-steps of the remaining time with scheme 2 (RKL2,
+ *     Fig. "rkl2") or 1 (RKL1: Y_1 = Y_0 + w1 h F(Y_0), Y_j = mu_j Y_{j-1} +
+ *     nu_j Y_{j-2} + mu~_j h F(Y_{j-1}), mu_j = (2j-1)/j, nu_j = -(j-1)/j,
+ *     mu~_j = w1 (2j-1)/j, w1 = 2/(s^2+s)), each with the minimal stable s
+ *     for its length (RKL2: Eq. rkl2_s; RKL1: s^2 + s >= 2 h/dt_E) plus
+ *     extra (>= 0) stages, rounded up to odd if odd != 0.
+ * In place on u (ncomp components).  *n_apply (may be NULL) receives the
+ * number of operator evaluations.  The FP32 form accepts RKL2 sub-steps only
+ * (STS_EINVAL otherwise).  */
+sts_status rkl_step(sts_ctx *ctx, double *u, int ncomp, double dt, int scheme, int extra, int odd,
+                    int nsub, double euler_fraction, double euler_cfl, int *n_apply);
+
 /* be_pcg_solve - one backward-Euler step (Sec. 2.1, Eqs. BE, BE_lin,
  * BE_linsolve) written as (V - dt S) u^{n+1} = V u^n + dt g and solved by the
  * PCG of Fig. "pcg" (Sec. 2.2).  u_n: u^n (read only).  x: on entry the

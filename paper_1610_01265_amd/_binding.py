@@ -55,6 +55,7 @@ def load():
         "sts_dt_euler": (I, [P, PD]),
         "apply_F": (I, [P, P, P, I]),
         "rkl2_step": (I, [P, P, I, D, I, PI]),
+        "rkl_step": (I, [P, P, I, D, I, I, I, I, D, D, PI]),
         "be_pcg_solve": (I, [P, P, P, D, I, PI, D, I, PI, PD]),
         "sts_be_residual": (I, [P, P, P, D, PD]),
         "cnn_create": (I, [ctypes.POINTER(P), P, I, I]),
@@ -82,7 +83,7 @@ def load():
 def exported_symbols():
     return ["sts_create", "sts_destroy", "sts_set_stream", "sts_last_error", "sts_num_cells",
             "sts_set_spitzer", "sts_set_isotropic", "sts_set_spitzer_f32", "sts_set_isotropic_f32",
-            "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "be_pcg_solve",
+            "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "rkl_step", "be_pcg_solve",
             "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
             "cnn_get_weights", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
             "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_guess"]
@@ -207,6 +208,17 @@ class Context:
         self._check(self._lib.rkl2_step(self._h, _ptr(u, self.ncell, "u", nc), nc, float(dt),
                                         int(s), ctypes.byref(used)))
         return used.value
+
+    def rkl_step(self, u, dt, scheme=2, extra=0, odd=False, nsub=1, euler_fraction=0.0,
+                 euler_cfl=0.5) -> int:
+        """Super-step variants (see include/sts.h); returns the operator evaluations."""
+        self._sync_stream()
+        nc = self._ncomp(u)
+        n = ctypes.c_int()
+        self._check(self._lib.rkl_step(self._h, _ptr(u, self.ncell, "u", nc), nc, float(dt),
+                                       int(scheme), int(extra), int(bool(odd)), int(nsub),
+                                       float(euler_fraction), float(euler_cfl), ctypes.byref(n)))
+        return n.value
 
     def be_pcg_solve(self, u_n, x, dt, pc=PC_JACOBI, block=(8, 8, 8), rtol=1e-8, maxit=10000,
                      allow_not_converged=False):
@@ -399,6 +411,11 @@ def apply_F(ctx: Context, u, out=None):
 
 def rkl2_step(ctx: Context, u, dt, s=0) -> int:
     return ctx.rkl2_step(u, dt, s)
+
+
+def rkl_step(ctx: Context, u, dt, scheme=2, extra=0, odd=False, nsub=1, euler_fraction=0.0,
+             euler_cfl=0.5) -> int:
+    return ctx.rkl_step(u, dt, scheme, extra, odd, nsub, euler_fraction, euler_cfl)
 
 
 def be_pcg_solve(ctx: Context, u_n, x, dt, pc=PC_JACOBI, block=(8, 8, 8), rtol=1e-8,

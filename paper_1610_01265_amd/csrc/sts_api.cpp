@@ -483,23 +483,8 @@ static sts_status rkl2_step_f32(sts_ctx *ctx, double *u, int ncomp, double dt, i
   return STS_OK;
 }
 
-sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used) {
-  if (!ctx) return STS_EINVAL;
-  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
-  if (!u) FAIL(STS_EINVAL, "rkl2_step: null u");
-  if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, "rkl2_step: ncomp must be in [1, 16]");
-  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "rkl2_step: dt must be finite, > 0");
-  if (s <= 0) {
-    double dte;
-    sts_status st = sts_dt_euler(ctx, &dte);
-    if (st) return st;
-    const double ratio = dt / dte;
-    if (!(ratio < 0.25 * kMaxStages * (double)kMaxStages)) FAIL(STS_EINVAL, "dt too large");
-    s = stage_count(ratio);
-  }
-  if (s < 2 || s > kMaxStages) FAIL(STS_EINVAL, "rkl2_step: s must be >= 2");
-  if (s_used) *s_used = s;
-  if (ctx->prec == 1) return rkl2_step_f32(ctx, u, ncomp, dt, s);
+// RKL workspace: F0 and the state buffers, ncell * ncomp each
+static sts_status rk_workspace(sts_ctx *ctx, int ncomp) {
   const long long n = ctx->ncell * ncomp;
   if (ctx->rk_ncomp < ncomp) {
     dfree(ctx->d_rk);
@@ -508,13 +493,32 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
     if (st) return st;
     ctx->rk_ncomp = ncomp;
   }
+  return STS_OK;
+}
+
+// One super-step of s stages in FP64: scheme 2 = RKL2 (Sec. 3, Fig. "rkl2"),
+// scheme 1 = RKL1 (the first-order member of the same family).
+static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int scheme) {
+  sts_status st0 = rk_workspace(ctx, ncomp);
+  if (st0) return st0;
+  const long long n = ctx->ncell * ncomp;
   double *F0 = ctx->d_rk;
   double *P[kRkBuffers];
   for (int q = 0; q < kRkBuffers; ++q) P[q] = ctx->d_rk + (1 + q) * n;
   // stage coefficients (Sec. 3): b_k, mu_k, nu_k, mu~_k, gamma~_k
   const double ss = (double)s * s + s - 2.0;
   auto bk = [](int k) { return k <= 2 ? 1.0 / 3.0 : ((double)k * k + k - 2.0) / (2.0 * k * (k + 1.0)); };
+  // RKL1 (scheme 1): mu_k = (2k-1)/k, nu_k = -(k-1)/k, mu~_k = w1 (2k-1)/k,
+  // w1 = 2/(s^2+s), no u_0 or F0 terms (mu_k + nu_k = 1, gamma~_k = 0)
+  const double w1r1 = 2.0 / ((double)s * s + s);
   auto coef = [&](int k, double out[4]) {
+    if (scheme == 1) {
+      out[0] = (2.0 * k - 1.0) / k;
+      out[1] = -(k - 1.0) / k;
+      out[2] = w1r1 * (2.0 * k - 1.0) / k * dt;
+      out[3] = 0.0;
+      return;
+    }
     const double b = bk(k), b1 = bk(k - 1), b2 = bk(k - 2);
     const double mut = 4.0 * (2.0 * k - 1.0) / (k * ss) * b / b1;
     out[0] = (2.0 * k - 1.0) / k * b / b1;  // mu_k
@@ -522,8 +526,13 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
     out[2] = mut * dt;                      // mu~_k dt
     out[3] = -(1.0 - b1) * mut * dt;        // gamma~_k dt
   };
-  const double w1 = 4.0 / ss;
-  launch_stage(ctx, 1, ncomp, u, nullptr, u, F0, P[0], 0, 0, (w1 / 3.0) * dt, 0);
+  const double mut1 = scheme == 1 ? w1r1 * dt : (4.0 / ss / 3.0) * dt;
+  launch_stage(ctx, 1, ncomp, u, nullptr, u, F0, P[0], 0, 0, mut1, 0);
+  LAUNCHCHK();
+  if (s == 1) {  // RKL1 with one stage: explicit Euler
+    HIPCHK(hipMemcpyAsync(u, P[0], (size_t)n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    return STS_OK;
+  }
   LAUNCHCHK();
   // u_{k-1} in prev1, u_{k-2} in prev2 (u_0 = u for k = 2).  Pairs of stages
   // write into buffers that hold neither input; a single stage overwrites
@@ -539,7 +548,7 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
   while (k <= s) {
     double c1[4];
     coef(k, c1);
-    if (kRkFuse && k + 1 < s) {
+    if (kRkFuse && scheme == 2 && k + 1 < s) {
       double c2[4];
       coef(k + 1, c2);
       double *o1 = free_buf(prev1, prev2, nullptr);
@@ -562,6 +571,89 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
   return STS_OK;
 }
 
+sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used) {
+  if (!ctx) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (!u) FAIL(STS_EINVAL, "rkl2_step: null u");
+  if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, "rkl2_step: ncomp must be in [1, 16]");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "rkl2_step: dt must be finite, > 0");
+  if (s <= 0) {
+    double dte;
+    sts_status st = sts_dt_euler(ctx, &dte);
+    if (st) return st;
+    const double ratio = dt / dte;
+    if (!(ratio < 0.25 * kMaxStages * (double)kMaxStages)) FAIL(STS_EINVAL, "dt too large");
+    s = stage_count(ratio);
+  }
+  if (s < 2 || s > kMaxStages) FAIL(STS_EINVAL, "rkl2_step: s must be >= 2");
+  if (s_used) *s_used = s;
+  if (ctx->prec == 1) return rkl2_step_f32(ctx, u, ncomp, dt, s);
+  return rk_fp64(ctx, u, ncomp, dt, s, 2);
+}
+
+
+sts_status rkl_step(sts_ctx *ctx, double *u, int ncomp, double dt, int scheme, int extra,
+                    int odd, int nsub, double euler_fraction, double euler_cfl, int *n_apply) {
+  if (!ctx) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (!u) FAIL(STS_EINVAL, "rkl_step: null u");
+  if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, "rkl_step: ncomp must be in [1, 16]");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "rkl_step: dt must be finite, > 0");
+  if (scheme != 1 && scheme != 2) FAIL(STS_EINVAL, "rkl_step: scheme must be 1 or 2");
+  if (extra < 0 || extra > 1000) FAIL(STS_EINVAL, "rkl_step: extra must be in [0, 1000]");
+  if (nsub < 1 || nsub > 10000) FAIL(STS_EINVAL, "rkl_step: nsub must be in [1, 10000]");
+  if (!(euler_fraction >= 0.0 && euler_fraction < 1.0))
+    FAIL(STS_EINVAL, "rkl_step: euler_fraction must be in [0, 1)");
+  if (euler_fraction > 0.0 && !(euler_cfl > 0.0 && euler_cfl <= 1.0))
+    FAIL(STS_EINVAL, "rkl_step: euler_cfl must be in (0, 1]");
+  if (ctx->prec == 1 && (scheme != 2 || euler_fraction > 0.0))
+    FAIL(STS_EINVAL, "rkl_step: the FP32 form supports RKL2 sub-steps only");
+  double dte;
+  sts_status st = sts_dt_euler(ctx, &dte);
+  if (st) return st;
+  int napply = 0;
+  // explicit Euler sub-steps over euler_fraction * dt, each at most euler_cfl * dt_E
+  double rest = dt;
+  if (euler_fraction > 0.0) {
+    const double span = euler_fraction * dt;
+    const double ne = std::ceil(span / (euler_cfl * dte) - 1e-12);
+    if (!(ne < 1e7)) FAIL(STS_EINVAL, "rkl_step: too many Euler sub-steps");
+    const int n_e = std::max(1, (int)ne);
+    const double h = span / n_e;
+    if ((st = rk_workspace(ctx, ncomp))) return st;
+    const long long n = ctx->ncell * ncomp;
+    double *F0 = ctx->d_rk, *tmp = ctx->d_rk + n;
+    for (int q = 0; q < n_e; ++q) {
+      launch_stage(ctx, 1, ncomp, u, nullptr, u, F0, tmp, 0, 0, h, 0);  // tmp = u + h F(u)
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(u, tmp, (size_t)n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    napply += n_e;
+    rest = dt - n_e * h;
+  }
+  if (rest > 0.0) {
+    const double ds = rest / nsub, ratio = ds / dte;
+    if (!(ratio < 0.25 * kMaxStages * (double)kMaxStages)) FAIL(STS_EINVAL, "dt too large");
+    int s;
+    if (scheme == 2) {
+      s = stage_count(ratio) + extra;
+    } else {
+      s = std::max(1, (int)std::ceil((std::sqrt(1.0 + 8.0 * ratio) - 1.0) / 2.0));
+      while (s > 1 && (double)(s - 1) * s >= 2.0 * ratio) --s;
+      while ((double)s * s + s < 2.0 * ratio) ++s;
+      s += extra;
+    }
+    if (odd && s % 2 == 0) ++s;
+    if (s > kMaxStages) FAIL(STS_EINVAL, "rkl_step: too many stages");
+    for (int q = 0; q < nsub; ++q) {
+      st = ctx->prec == 1 ? rkl2_step_f32(ctx, u, ncomp, ds, s) : rk_fp64(ctx, u, ncomp, ds, s, scheme);
+      if (st) return st;
+    }
+    napply += nsub * s;
+  }
+  if (n_apply) *n_apply = napply;
+  return STS_OK;
+}
 
 static sts_status pcg_workspace(sts_ctx *ctx, int pc, const int block[3], double **fac) {
   const long long n = ctx->ncell;

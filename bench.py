@@ -11,7 +11,10 @@ One step = one pass of the whole path over the synthetic shell input:
   * artificial viscosity on a 3-component velocity field: RKL2 step of all
     three components and one Jacobi-PCG BE solve per component;
   * the learned initial guess: cnn_guess (network + residual fallback),
-    Jacobi-PCG from that guess, and one training step of the network.
+    Jacobi-PCG from that guess, and one training step of the network;
+  * the super-step variants of Sec. 6 on the temperature: RKL2 in 10
+    sub-cycles, explicit Euler over a quarter step then RKL2, and RKL1 with
+    one extra stage.
 Inputs are resident in HBM before the timed region.  Each phase is bracketed
 by HIP events on the library's stream.  `value` is the RKL2 throughput in
 cell-stage updates per second; the BE solve times are reported beside it.
@@ -49,7 +52,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="shell128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32,visc,learned",
+    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32,visc,learned,variants",
                     help="comma list of timed phases (profiling runs)")
     ap.add_argument("--learned-train-seeds", type=int, default=24,
                     help="training pairs (seeds 1..N) for the network before the timed steps")
@@ -248,6 +251,18 @@ def main():
         tm.mark("learned_train")
         if "learned" in phases:
             net.train_step(held.F, held.dt, held.T, held.x_star, 1e-4, want_loss=False)
+        tm.mark("var_subcycle10")
+        if "variants" in phases:
+            u.copy_(T)
+            info["n_sub10"] = ctx.rkl_step(u, dt, nsub=10)
+        tm.mark("var_euler_quarter")
+        if "variants" in phases:
+            u.copy_(T)
+            info["n_euler"] = ctx.rkl_step(u, dt, euler_fraction=0.25)
+        tm.mark("var_rkl1_extra1")
+        if "variants" in phases:
+            u.copy_(T)
+            info["n_rkl1"] = ctx.rkl_step(u, dt, scheme=1, extra=1)
         tm.mark("end")
         if rec is not None:
             rec.append((tm, info))
@@ -312,6 +327,13 @@ def main():
             "learned_guess_jacobi": ratio(t_jac, t_learn),
             "rkl2_step": ratio(t_jac, t_rk),
             "fp32_form_rkl2_step": ratio(t_jac, sec["fp32_rkl2"])},
+        "super_step_variants": {
+            "rkl2_10_subcycles": {"ms": ph.get("var_subcycle10"),
+                                  "operator_applications": info.get("n_sub10")},
+            "euler_quarter_then_rkl2": {"ms": ph.get("var_euler_quarter"),
+                                        "operator_applications": info.get("n_euler")},
+            "rkl1_one_extra_stage": {"ms": ph.get("var_rkl1_extra1"),
+                                     "operator_applications": info.get("n_rkl1")}},
         "learned": dict(learned_info, guess_used_net=info.get("guess_used_net"),
                         guess_relres_net_prev=info.get("guess_relres"),
                         train_step_ms=ph.get("learned_train")),

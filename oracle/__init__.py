@@ -17,7 +17,8 @@ Modules
   rkl2      - RKL2 super-time-stepping (Fig. "rkl2", coefficient block, Eq. rkl2_s)
   pcg       - backward Euler + preconditioned CG (Eqs. BE..BE_linsolve, Fig. "pcg")
   ilu0      - non-overlapping block ILU0 preconditioner (Appendix A, PC2)
-  precision - FP32-storage forms of RKL2 and BE (mixed precision)
+  rkl_variants - sub-cycled RKL2, Euler sub-steps, odd s and RKL1 (Sec. 6)
+  nonlinear - conduction with kappa taken from the current state (no lagging)
   cnn       - FP64 reference of the small 3D CNN used for learned initial guesses
 
 Parity status: every function is pinned by the CPU tests in

@@ -141,6 +141,33 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
 sts_status rkl_step(sts_ctx *ctx, double *u, int ncomp, double dt, int scheme, int extra, int odd,
                     int nsub, double euler_fraction, double euler_cfl, int *n_apply);
 
+/* apply_F_nonlinear - Fu = F(u) = V^-1 (S(kappa(u)) u + g(kappa(u))): the
+ * conduction operator of sts_set_spitzer with the diffusivity taken from u
+ * itself, kappa(u) = kappa0 max(u, 0)^{5/2}, D = kappa b b^T (Eq. mhd:e1,
+ * blue box; the operator RKL2 can apply without lagging, Sec. 2.4 and
+ * Sec. 3.1).  u, Fu, b0, b1, b2: device FP64 [n0][n1][n2]; b is the unit
+ * vector in the local basis; u and Fu must not overlap.  Uses the context's
+ * grid, boundaries and Dirichlet values only (no set_* call needed; the
+ * stored operator is left as it is).  Non-finite inputs give non-finite
+ * outputs; no input check is made.  */
+sts_status apply_F_nonlinear(sts_ctx *ctx, const double *u, double *Fu, double kappa0,
+                             const double *b0, const double *b1, const double *b2);
+
+/* rkl2_step_nonlinear - one RKL2 super-step (Sec. 3, Fig. "rkl2") of
+ * du/dt = F(u) with F the operator of apply_F_nonlinear: every stage takes
+ * kappa from its own input u_{k-1}, F0 = F(u^n), b fixed over the step.  In
+ * place on u (device FP64, u^n in, u^{n+1} out; one component).  The call
+ * first sets the context's operator to the lagged operator at u^n, as
+ * sts_set_spitzer(ctx, u, kappa0, b0, b1, b2) does (same input checks: u
+ * finite and > 0, b finite; STS_EINVAL otherwise, u untouched); s <= 0 takes
+ * the minimal stable s (Eq. rkl2_s) for dt / dt_E of that operator, s >= 2
+ * forces s.  *s_used (may be NULL) receives s.  Each stage is one kernel that
+ * forms the face / edge coefficients from u_{k-1} and b on the fly.
+ * Synchronises the stream (input check; dt_E when s <= 0).  */
+sts_status rkl2_step_nonlinear(sts_ctx *ctx, double *u, double dt, double kappa0,
+                               const double *b0, const double *b1, const double *b2, int s,
+                               int *s_used);
+
 /* be_pcg_solve - one backward-Euler step (Sec. 2.1, Eqs. BE, BE_lin,
  * BE_linsolve) written as (V - dt S) u^{n+1} = V u^n + dt g and solved by the
  * PCG of Fig. "pcg" (Sec. 2.2).  u_n: u^n (read only).  x: on entry the

@@ -56,6 +56,8 @@ def load():
         "apply_F": (I, [P, P, P, I]),
         "rkl2_step": (I, [P, P, I, D, I, PI]),
         "rkl_step": (I, [P, P, I, D, I, I, I, I, D, D, PI]),
+        "apply_F_nonlinear": (I, [P, P, P, D, P, P, P]),
+        "rkl2_step_nonlinear": (I, [P, P, D, D, P, P, P, I, PI]),
         "be_pcg_solve": (I, [P, P, P, D, I, PI, D, I, PI, PD]),
         "sts_be_residual": (I, [P, P, P, D, PD]),
         "cnn_create": (I, [ctypes.POINTER(P), P, I, I]),
@@ -83,7 +85,8 @@ def load():
 def exported_symbols():
     return ["sts_create", "sts_destroy", "sts_set_stream", "sts_last_error", "sts_num_cells",
             "sts_set_spitzer", "sts_set_isotropic", "sts_set_spitzer_f32", "sts_set_isotropic_f32",
-            "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "rkl_step", "be_pcg_solve",
+            "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "rkl_step",
+            "apply_F_nonlinear", "rkl2_step_nonlinear", "be_pcg_solve",
             "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
             "cnn_get_weights", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
             "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_guess"]
@@ -219,6 +222,27 @@ class Context:
                                        int(scheme), int(extra), int(bool(odd)), int(nsub),
                                        float(euler_fraction), float(euler_cfl), ctypes.byref(n)))
         return n.value
+
+    def apply_F_nonlinear(self, u, kappa0, b0, b1, b2, out=None):
+        """F(u) with kappa = kappa0 max(u, 0)^{5/2} taken from u (no lagging)."""
+        self._sync_stream()
+        n = self.ncell
+        if out is None:
+            out = torch.empty_like(u)
+        self._check(self._lib.apply_F_nonlinear(
+            self._h, _ptr(u, n, "u"), _ptr(out, n, "out"), float(kappa0), _ptr(b0, n, "b0"),
+            _ptr(b1, n, "b1"), _ptr(b2, n, "b2")))
+        return out
+
+    def rkl2_step_nonlinear(self, u, dt, kappa0, b0, b1, b2, s=0) -> int:
+        """RKL2 super-step with kappa taken from every stage value; returns s."""
+        self._sync_stream()
+        n = self.ncell
+        used = ctypes.c_int()
+        self._check(self._lib.rkl2_step_nonlinear(
+            self._h, _ptr(u, n, "u"), float(dt), float(kappa0), _ptr(b0, n, "b0"),
+            _ptr(b1, n, "b1"), _ptr(b2, n, "b2"), int(s), ctypes.byref(used)))
+        return used.value
 
     def be_pcg_solve(self, u_n, x, dt, pc=PC_JACOBI, block=(8, 8, 8), rtol=1e-8, maxit=10000,
                      allow_not_converged=False):
@@ -411,6 +435,14 @@ def apply_F(ctx: Context, u, out=None):
 
 def rkl2_step(ctx: Context, u, dt, s=0) -> int:
     return ctx.rkl2_step(u, dt, s)
+
+
+def apply_F_nonlinear(ctx: Context, u, kappa0, b0, b1, b2, out=None):
+    return ctx.apply_F_nonlinear(u, kappa0, b0, b1, b2, out)
+
+
+def rkl2_step_nonlinear(ctx: Context, u, dt, kappa0, b0, b1, b2, s=0) -> int:
+    return ctx.rkl2_step_nonlinear(u, dt, kappa0, b0, b1, b2, s)
 
 
 def rkl_step(ctx: Context, u, dt, scheme=2, extra=0, odd=False, nsub=1, euler_fraction=0.0,

@@ -496,9 +496,17 @@ static sts_status rk_workspace(sts_ctx *ctx, int ncomp) {
   return STS_OK;
 }
 
+// The conduction operator with kappa taken from each stage value (nullptr:
+// the context's stored operator).
+struct NlSpitzer {
+  double kappa0;
+  const double *b0, *b1, *b2;
+};
+
 // One super-step of s stages in FP64: scheme 2 = RKL2 (Sec. 3, Fig. "rkl2"),
 // scheme 1 = RKL1 (the first-order member of the same family).
-static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int scheme) {
+static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int scheme,
+                          const NlSpitzer *nl = nullptr) {
   sts_status st0 = rk_workspace(ctx, ncomp);
   if (st0) return st0;
   const long long n = ctx->ncell * ncomp;
@@ -527,7 +535,16 @@ static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, 
     out[3] = -(1.0 - b1) * mut * dt;        // gamma~_k dt
   };
   const double mut1 = scheme == 1 ? w1r1 * dt : (4.0 / ss / 3.0) * dt;
-  launch_stage(ctx, 1, ncomp, u, nullptr, u, F0, P[0], 0, 0, mut1, 0);
+  auto stage = [&](int mode, const double *ukm1, const double *ukm2, double *out,
+                   const double c[4]) {
+    if (nl)
+      launch_stage_nl(ctx, mode, ukm1, ukm2, u, F0, out, c[0], c[1], c[2], c[3], nl->kappa0,
+                      nl->b0, nl->b1, nl->b2);
+    else
+      launch_stage(ctx, mode, ncomp, ukm1, ukm2, u, F0, out, c[0], c[1], c[2], c[3]);
+  };
+  const double c1st[4] = {0.0, 0.0, mut1, 0.0};
+  stage(1, u, nullptr, P[0], c1st);
   LAUNCHCHK();
   if (s == 1) {  // RKL1 with one stage: explicit Euler
     HIPCHK(hipMemcpyAsync(u, P[0], (size_t)n * 8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -548,7 +565,7 @@ static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, 
   while (k <= s) {
     double c1[4];
     coef(k, c1);
-    if (kRkFuse && scheme == 2 && k + 1 < s) {
+    if (kRkFuse && !nl && scheme == 2 && k + 1 < s) {
       double c2[4];
       coef(k + 1, c2);
       double *o1 = free_buf(prev1, prev2, nullptr);
@@ -561,7 +578,7 @@ static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, 
     } else {
       // a single stage reads u_{k-2} only at its own cell: it may overwrite it
       double *out = (k == s) ? u : (prev2 != u ? (double *)prev2 : free_buf(prev1, prev2, nullptr));
-      launch_stage(ctx, 2, ncomp, prev1, prev2, u, F0, out, c1[0], c1[1], c1[2], c1[3]);
+      stage(2, prev1, prev2, out, c1);
       LAUNCHCHK();
       prev2 = prev1;
       prev1 = out;
@@ -591,6 +608,42 @@ sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *
   return rk_fp64(ctx, u, ncomp, dt, s, 2);
 }
 
+
+sts_status apply_F_nonlinear(sts_ctx *ctx, const double *u, double *Fu, double kappa0,
+                             const double *b0, const double *b1, const double *b2) {
+  if (!ctx) return STS_EINVAL;
+  if (!u || !Fu || u == Fu) FAIL(STS_EINVAL, "apply_F_nonlinear: null or aliased arrays");
+  if (!b0 || !b1 || !b2) FAIL(STS_EINVAL, "apply_F_nonlinear: null b");
+  if (!(kappa0 > 0.0) || !std::isfinite(kappa0)) FAIL(STS_EINVAL, "kappa0 must be finite, > 0");
+  sts_status st = refresh_dirichlet_values(ctx);
+  if (st) return st;
+  launch_stage_nl(ctx, 0, u, nullptr, nullptr, nullptr, Fu, 0, 0, 0, 0, kappa0, b0, b1, b2);
+  LAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status rkl2_step_nonlinear(sts_ctx *ctx, double *u, double dt, double kappa0,
+                               const double *b0, const double *b1, const double *b2, int s,
+                               int *s_used) {
+  if (!ctx) return STS_EINVAL;
+  if (!u) FAIL(STS_EINVAL, "rkl2_step_nonlinear: null u");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    FAIL(STS_EINVAL, "rkl2_step_nonlinear: dt must be finite, > 0");
+  if (s > kMaxStages || s == 1) FAIL(STS_EINVAL, "rkl2_step_nonlinear: s must be >= 2");
+  // the operator at u^n: input checks, Dirichlet weights, dt_E
+  sts_status st = sts_set_spitzer(ctx, u, kappa0, b0, b1, b2);
+  if (st) return st;
+  if (s <= 0) {
+    double dte;
+    if ((st = sts_dt_euler(ctx, &dte))) return st;
+    const double ratio = dt / dte;
+    if (!(ratio < 0.25 * kMaxStages * (double)kMaxStages)) FAIL(STS_EINVAL, "dt too large");
+    s = stage_count(ratio);
+  }
+  if (s_used) *s_used = s;
+  const NlSpitzer nl{kappa0, b0, b1, b2};
+  return rk_fp64(ctx, u, 1, dt, s, 2, &nl);
+}
 
 sts_status rkl_step(sts_ctx *ctx, double *u, int ncomp, double dt, int scheme, int extra,
                     int odd, int nsub, double euler_fraction, double euler_cfl, int *n_apply) {

@@ -137,6 +137,13 @@ void launch_stage2(const sts_ctx *c, int ncomp, const double *ukm1, const double
                    const double *u0, const double *F0, double *out1, double *out2,
                    const double st1[4], const double st2[4]);
 
+// Conduction with kappa = kappa0 max(u, 0)^{5/2} taken from the stencil
+// input itself (k_nonlinear.hip); modes as launch_stage, one component.
+void launch_stage_nl(const sts_ctx *c, int mode, const double *ukm1, const double *ukm2,
+                     const double *u0, double *F0, double *out, double mu, double nu,
+                     double mut_dt, double gt_dt, double kappa0, const double *b0,
+                     const double *b1, const double *b2);
+
 // FP32 form (k_stencil.hip, k_pcg.hip)
 void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1, double mut_dt);
 void f32_apply(const sts_ctx *c, int ncomp, const double *u, double *Fu);

@@ -14,7 +14,9 @@ One step = one pass of the whole path over the synthetic shell input:
     Jacobi-PCG from that guess, and one training step of the network;
   * the super-step variants of Sec. 6 on the temperature: RKL2 in 10
     sub-cycles, explicit Euler over a quarter step then RKL2, and RKL1 with
-    one extra stage.
+    one extra stage;
+  * RKL2 with the diffusivity taken from every stage value (no lagging):
+    one rkl2_step_nonlinear (its own set-up at u^n included).
 Inputs are resident in HBM before the timed region.  Each phase is bracketed
 by HIP events on the library's stream.  `value` is the RKL2 throughput in
 cell-stage updates per second; the BE solve times are reported beside it.
@@ -42,7 +44,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_rkl2_stage_shell128_pmc.txt")
-STAGE_SOURCES = ["k_stencil.hip", "k_common.h", "sts_internal.h"]
+STAGE_SOURCES = ["k_stencil.hip", "k_row.h", "k_common.h", "sts_internal.h"]
 
 
 def parse():
@@ -52,7 +54,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="shell128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32,visc,learned,variants",
+    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32,visc,learned,variants,nonlinear",
                     help="comma list of timed phases (profiling runs)")
     ap.add_argument("--learned-train-seeds", type=int, default=24,
                     help="training pairs (seeds 1..N) for the network before the timed steps")
@@ -129,6 +131,27 @@ class Timer:
         for (a, ea), (_, eb) in zip(self.marks, self.marks[1:]):
             out[a] = out.get(a, 0.0) + ea.elapsed_time(eb)
         return out  # ms
+
+
+def nonlinear_entry(ph, info, ncell):
+    """RKL2 with kappa from every stage value against the lagged protocol
+    (coefficient set-up + RKL2 step).  Stage kernel bytes: 48 B/cell for stage
+    1 (u, b read; F0, u_1 written), 64 B/cell for stages 2..s (u_{k-1}, b,
+    u_{k-2}, u_0, F0 read; u_k written); its mean launch time is estimated as
+    (phase - set-up) / s."""
+    s = info.get("s_nl")
+    if not s or "nl_rkl2" not in ph:
+        return None
+    t = ph["nl_rkl2"]
+    lagged = ph.get("setup", 0.0) + ph.get("rkl2", 0.0)
+    stage_us = max(t - ph.get("setup", 0.0), 0.0) / s * 1e3
+    alg = (48 + 64 * (s - 1)) * ncell / s
+    gbs = alg / (stage_us * 1e-6) / 1e9 if stage_us > 0 else None
+    return {"ms": t, "stages": s, "lagged_setup_plus_rkl2_ms": lagged,
+            "time_vs_lagged": t / lagged if lagged > 0 else None,
+            "stage_kernel": {"mean_launch_us_est": stage_us, "alg_bytes_per_launch": alg,
+                             "achieved_GBs": gbs,
+                             "frac_hbm": gbs / HBM_PEAK_GBS if gbs else None}}
 
 
 def main():
@@ -263,6 +286,10 @@ def main():
         if "variants" in phases:
             u.copy_(T)
             info["n_rkl1"] = ctx.rkl_step(u, dt, scheme=1, extra=1)
+        tm.mark("nl_rkl2")
+        if "nonlinear" in phases:
+            u.copy_(T)
+            info["s_nl"] = ctx.rkl2_step_nonlinear(u, dt, w["kappa0"], br, bt, bp)
         tm.mark("end")
         if rec is not None:
             rec.append((tm, info))
@@ -334,6 +361,7 @@ def main():
                                         "operator_applications": info.get("n_euler")},
             "rkl1_one_extra_stage": {"ms": ph.get("var_rkl1_extra1"),
                                      "operator_applications": info.get("n_rkl1")}},
+        "nonlinear_kappa_rkl2": nonlinear_entry(ph, info, ncell),
         "learned": dict(learned_info, guess_used_net=info.get("guess_used_net"),
                         guess_relres_net_prev=info.get("guess_relres"),
                         train_step_ms=ph.get("learned_train")),

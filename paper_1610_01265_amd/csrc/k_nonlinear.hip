@@ -29,7 +29,7 @@ namespace sts {
 namespace {
 
 #ifndef STS_NL_WG
-#define STS_NL_WG 2048
+#define STS_NL_WG 512  // about one round of 2 workgroups per CU
 #endif
 
 constexpr int NK = 64, NJ = 4, NNT = NK * NJ;          // tile = threads
@@ -82,17 +82,6 @@ __device__ __forceinline__ void ring_cell(int r, int &hj, int &hk) {
     hj = r - 2 * QK - NJ + 1;
     hk = NK + 1;
   }
-}
-
-// Table reads at a wavefront-uniform index, through the constant address
-// space so that they become scalar loads: a vector load here would make the
-// row wait (in-order vmcnt) for the next plane's prefetch issued before it.
-typedef const __attribute__((address_space(4))) double cdouble;
-__device__ __forceinline__ double T0u(const Grid &g, int t, int i) {
-  return ((cdouble *)g.t0)[t * g.n0 + i];
-}
-__device__ __forceinline__ double T1u(const Grid &g, int t, int j) {
-  return ((cdouble *)g.t1)[t * g.n1 + j];
 }
 
 // r-direction geometry of plane i: A00 IL00, A10 IL10, A20 IL20, V0 and

@@ -9,6 +9,18 @@ namespace sts {
 
 namespace {
 
+// Table reads at a wavefront-uniform index, through the constant address
+// space so that they become scalar loads: as vector loads they would join the
+// in-order count of outstanding vector loads, and waiting for them would also
+// wait for every load issued before them (the next plane's prefetch).
+typedef const __attribute__((address_space(4))) double cdouble;
+__device__ __forceinline__ double T0u(const Grid &g, int t, int i) {
+  return ((cdouble *)g.t0)[t * g.n0 + i];
+}
+__device__ __forceinline__ double T1u(const Grid &g, int t, int j) {
+  return ((cdouble *)g.t1)[t * g.n1 + j];
+}
+
 // Index along an axis for a position that may lie outside [0, n): periodic
 // axes wrap (a tile may be wider than a short axis, so use a full modulo),
 // others clamp.

@@ -31,17 +31,21 @@ namespace {
 #define STS_MARCH_TJ 4
 #endif
 #ifndef STS_MARCH_WG
-#define STS_MARCH_WG 2048
+#define STS_MARCH_WG 1024  // about one round of 4 workgroups per CU
 #endif
 // STS_PF: per-cell operands loaded one plane ahead (1), only the cell's own
 // streams one plane ahead (2), or all at their plane (0).
 // STS_HALO: the stencil-input plane staged into LDS at the end of iteration i
-// is loaded during iteration i (1) or during iteration i - 1 (2).
+// is loaded during iteration i before (1) or after (3) this plane's per-cell
+// loads, or during iteration i - 1 (2).  Vector loads complete in order, so in
+// (1) and (2) the row's wait for its per-cell operands also waits for the
+// prefetch; (3) issues the prefetch last and unconditionally (same loads on
+// every lane and iteration), so it stays in flight across the row.
 #ifndef STS_PF
 #define STS_PF 0
 #endif
 #ifndef STS_HALO
-#define STS_HALO 2
+#define STS_HALO 3
 #endif
 constexpr int TK = 64, TJ = STS_MARCH_TJ, NT = TK * TJ;
 constexpr int HK = TK + 2, HJ = TJ + 2, PL = HK * HJ;  // one LDS plane (tile + halo)
@@ -100,7 +104,7 @@ struct Args {
 };
 
 #ifndef STS_MARCH_WPE
-#define STS_MARCH_WPE 1
+#define STS_MARCH_WPE 4  // waves per SIMD the register allocation must allow
 #endif
 template <int OP, int MODE, class Loader, class CT>
 __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
@@ -109,7 +113,10 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   if (MODE == M_PA && a.sc->done) return;
   __shared__ R s_u[4][PL];
   ld.prepare();
-  const int tk = threadIdx.x, tj = threadIdx.y, tid = tj * TK + tk;
+  // a wavefront is one tile row (blockDim.x = 64): theta-dependent values
+  // are uniform across it
+  const int tk = threadIdx.x, tj = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int tid = tj * TK + tk;
   // XCD-aware order: workgroup w runs on XCD w % 8; each XCD gets a
   // contiguous range of the logical (chunk, row-tile, column-tile) order.
   const int nwg = gridDim.x, w = blockIdx.x;
@@ -156,11 +163,11 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   ThreadGeo<R> tg;
   tg.B = nbr(jc, g.n1, g.per1);
   tg.C = nbr(kc, g.n2, g.per2);
-  tg.t11m = T1(g, T_IL11, tg.B.m);
-  tg.t11 = T1(g, T_IL11, jc);
-  tg.t21m = T1(g, T_IL21, tg.B.m);
-  tg.t21 = T1(g, T_IL21, jc);
-  tg.t21p = T1(g, T_IL21, tg.B.p);
+  tg.t11m = T1u(g, T_IL11, tg.B.m);
+  tg.t11 = T1u(g, T_IL11, jc);
+  tg.t21m = T1u(g, T_IL21, tg.B.m);
+  tg.t21 = T1u(g, T_IL21, jc);
+  tg.t21p = T1u(g, T_IL21, tg.B.p);
   tg.t22m = T2(g, T_IL22, tg.C.m);
   tg.t22 = T2(g, T_IL22, kc);
   tg.v12 = T1(g, T_V1, jc) * T2(g, T_V2, kc);
@@ -247,7 +254,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     const bool pre = i + 2 <= i1;
     if (STS_HALO == 1) {
       if (pre) load_plane(i + 2, v);
-    } else {
+    } else if (STS_HALO == 2) {
       if (i + 3 <= i1) load_plane(i + 3, vn);
     }
     if (STS_PF == 1) {
@@ -258,23 +265,24 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     } else {
       load_plane_cells(i, cur);
     }
+    if (STS_HALO == 3) load_plane(i + 2, v);
     if (active) {
       PlaneGeo<R> pg;
       pg.A = nbr(i, g.n0, g.per0);
-      pg.s00m = T0(g, T_IL00, pg.A.m);
-      pg.s00 = T0(g, T_IL00, i);
-      pg.s10m = T0(g, T_IL10, pg.A.m);
-      pg.s10 = T0(g, T_IL10, i);
-      pg.s10p = T0(g, T_IL10, pg.A.p);
-      pg.s20m = T0(g, T_IL20, pg.A.m);
-      pg.s20 = T0(g, T_IL20, i);
-      pg.s20p = T0(g, T_IL20, pg.A.p);
-      pg.v0 = T0(g, T_V0, i);
+      pg.s00m = T0u(g, T_IL00, pg.A.m);
+      pg.s00 = T0u(g, T_IL00, i);
+      pg.s10m = T0u(g, T_IL10, pg.A.m);
+      pg.s10 = T0u(g, T_IL10, i);
+      pg.s10p = T0u(g, T_IL10, pg.A.p);
+      pg.s20m = T0u(g, T_IL20, pg.A.m);
+      pg.s20 = T0u(g, T_IL20, i);
+      pg.s20p = T0u(g, T_IL20, pg.A.p);
+      pg.v0 = T0u(g, T_V0, i);
       if (OP == OP_ISOTROPIC) {
-        pg.a00 = T0(g, T_A00, i);
-        pg.a00m = T0(g, T_A00, pg.A.m);
-        pg.a10 = T0(g, T_A10, i);
-        pg.a20 = T0(g, T_A20, i);
+        pg.a00 = T0u(g, T_A00, i);
+        pg.a00m = T0u(g, T_A00, pg.A.m);
+        pg.a10 = T0u(g, T_A10, i);
+        pg.a20 = T0u(g, T_A20, i);
       }
       const int base = (tj + 1) * HK + (tk + 1);
       const R *sm = s_u[(i - 1) & 3], *s0 = s_u[i & 3], *sp = s_u[(i + 1) & 3];

@@ -41,6 +41,26 @@ __device__ __forceinline__ Nb nbr(int i, int n, int per) {
   return r;
 }
 
+// Operands the FP64 RKL2 stage reads or writes once per sweep (u_{k-2}, u_0,
+// F0, u_k) are accessed non-temporally, leaving the caches to the halo and
+// neighbour-coefficient re-reads (STS_NT=0 turns this off).  Measured per
+// kernel: the FP32 stages and the PCG sweeps ran slower this way.
+#ifndef STS_NT
+#define STS_NT 1
+#endif
+template <class T>
+__device__ __forceinline__ T stream_ld(const T *p) {
+  if (STS_NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <class T>
+__device__ __forceinline__ void stream_st(T *p, T v) {
+  if (STS_NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 __device__ __forceinline__ double T0(const Grid &g, int t, int i) { return g.t0[t * g.n0 + i]; }
 __device__ __forceinline__ double T1(const Grid &g, int t, int j) { return g.t1[t * g.n1 + j]; }
 __device__ __forceinline__ double T2(const Grid &g, int t, int k) { return g.t2[t * g.n2 + k]; }

@@ -207,10 +207,18 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     }
     const long long cc = off + c;
     if (MODE == M_RK || MODE == M_DK || MODE == M_DLAST) {
-      L.x0 = ((const R *)a.ukm2)[cc];
-      L.x2 = ((const R *)a.F0)[cc];
+      // FP64 stages stream these operands non-temporally; the FP32 stages
+      // measured slower that way
+      if (MODE == M_RK) {
+        L.x0 = stream_ld(&((const R *)a.ukm2)[cc]);
+        L.x2 = stream_ld(&((const R *)a.F0)[cc]);
+      } else {
+        L.x0 = ((const R *)a.ukm2)[cc];
+        L.x2 = ((const R *)a.F0)[cc];
+      }
     }
-    if (MODE == M_RK || MODE == M_DLAST) L.x1 = a.u0[cc];
+    if (MODE == M_RK) L.x1 = stream_ld(&a.u0[cc]);
+    if (MODE == M_DLAST) L.x1 = a.u0[cc];
     if (MODE == M_RES || MODE == M_RESN) L.x1 = a.b[cc];
   };
   // same-plane neighbour coefficients of plane ip (loaded by neighbouring
@@ -325,13 +333,13 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
         if (a.out) ((float *)a.out)[cc] = (float)a.mut_dt * F;  // delta_1 = mu~_1 dt F0
       } else if (MODE == M_RK1) {
         const R F = su / V;
-        ((R *)a.F0)[cc] = F;
-        ((R *)a.out)[cc] = uc + R(a.mut_dt) * F;
+        stream_st(&((R *)a.F0)[cc], F);
+        stream_st(&((R *)a.out)[cc], uc + R(a.mut_dt) * F);
       } else if (MODE == M_RK) {
         const R F = su / V;
-        ((R *)a.out)[cc] = R(a.mu) * uc + R(a.nu) * cur.x0 +
-                           (R(1) - R(a.mu) - R(a.nu)) * R(cur.x1) + R(a.mut_dt) * F +
-                           R(a.gt_dt) * cur.x2;
+        stream_st(&((R *)a.out)[cc], R(a.mu) * uc + R(a.nu) * cur.x0 +
+                                         (R(1) - R(a.mu) - R(a.nu)) * R(cur.x1) +
+                                         R(a.mut_dt) * F + R(a.gt_dt) * cur.x2);
       } else if (MODE == M_DK || MODE == M_DLAST) {
         // delta_k = mu delta_{k-1} + nu delta_{k-2} + mu~ dt M delta_{k-1}
         //           + (mu~ + gamma~) dt F0      (gt_dt carries (mu~ + gamma~) dt)

@@ -324,21 +324,33 @@ __global__ void __launch_bounds__(256)
 }
 
 // g[co][ci][tap] (the master-weight layout) and g_bias[co] = sums over the
-// workgroups' partials part[w][q][co][ci], in workgroup order.
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, float *__restrict__ g) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= NTAP * 256 + CC) return;
-  size_t src;
-  if (idx < NTAP * 256) {
-    const int tap = idx % NTAP, cc = idx / NTAP;
-    src = (size_t)tap * 256 + cc;
-  } else {
-    src = (size_t)NTAP * 256 + (idx - NTAP * 256) * 16;  // bias: column ci = 0
-  }
+// workgroups' partials part[w][q][co][ci].  Coalesced: a workgroup owns 32
+// consecutive entries of the partial layout and splits the workgroup range
+// into 8 slices, each summed in order, the slices then in order (a fixed
+// summation order: deterministic).
+constexpr int WR_OUT = 32, WR_SLICES = 8;
+__global__ void __launch_bounds__(WR_OUT *WR_SLICES)
+    k_wgrad_reduce(const float *__restrict__ part, int nwg, float *__restrict__ g) {
+  __shared__ float red[WR_SLICES][WR_OUT];
+  const int o = threadIdx.x % WR_OUT, sl = threadIdx.x / WR_OUT;
+  const int idx = blockIdx.x * WR_OUT + o;  // = q * 256 + cc
   const size_t stride = (size_t)(NTAP + 1) * 256;
+  const int per = (nwg + WR_SLICES - 1) / WR_SLICES;
+  const int w0 = sl * per, w1 = min(nwg, w0 + per);
   float s = 0.f;
-  for (int w = 0; w < nwg; ++w) s += part[w * stride + src];
-  g[idx] = s;
+  for (int w = w0; w < w1; ++w) s += part[w * stride + idx];
+  red[sl][o] = s;
+  __syncthreads();
+  if (sl == 0) {
+    float t = red[0][o];
+#pragma unroll
+    for (int q = 1; q < WR_SLICES; ++q) t += red[q][o];
+    const int q = idx >> 8, cc = idx & 255;
+    if (q < NTAP)
+      g[cc * NTAP + q] = t;
+    else if ((cc & 15) == 0)
+      g[NTAP * 256 + (cc >> 4)] = t;  // bias: column ci = 0
+  }
 }
 
 // Network input: channel 0 = rhs * rs, channel 1 = (T - ts) * tsc, others 0.
@@ -490,8 +502,8 @@ void launch_cnn_wgrad(const CnnLaunch &L, const void *act, const void *dout, flo
   const int nwg = std::min(nitems, cnn_wgrad_parts());
   hipLaunchKernelGGL(k_wgrad, dim3(nwg), dim3(256), 0, L.stream, gr, (const __bf16 *)act,
                      (const __bf16 *)dout, part, CI, nitems);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((NTAP * 256 + CC + 255) / 256), dim3(256), 0, L.stream,
-                     part, nwg, g);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((NTAP + 1) * 256 / WR_OUT), dim3(WR_OUT * WR_SLICES), 0,
+                     L.stream, part, nwg, g);
 }
 
 void launch_cnn_pack_input(const CnnLaunch &L, const double *rhs, const double *T, double rs, double tsh,

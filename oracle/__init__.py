@@ -19,6 +19,7 @@ Modules
   ilu0      - non-overlapping block ILU0 preconditioner (Appendix A, PC2)
   rkl_variants - sub-cycled RKL2, Euler sub-steps, odd s and RKL1 (Sec. 6)
   nonlinear - conduction with kappa taken from the current state (no lagging)
+  resistivity - edge-staggered curl curl A (Eq. mhd:a) and its BE + PC1 solve
   cnn       - FP64 reference of the small 3D CNN used for learned initial guesses
 
 Parity status: every function is pinned by the CPU tests in

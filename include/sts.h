@@ -183,6 +183,48 @@ sts_status rkl2_step_nonlinear(sts_ctx *ctx, double *u, double dt, double kappa0
 sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, int pc,
                         const int block[3], double rtol, int maxit, int *iters, double *relres);
 
+/* Resistive diffusion of the vector potential, dA/dt = -eta curl curl A
+ * (Eq. mhd:a, boxed; eta stands for c^2 eta / 4 pi, constant as in the
+ * paper's runs), advanced by BE + PCG with PC1 as MAS does for this term
+ * (Sec. 4.2).  A is staggered on the cell edges (MAS keeps every vector
+ * component staggered so that div B = 0 holds exactly): the unknowns are the
+ * line integrals E = A . dl along the edges, one device FP64 vector
+ * [E_r | E_t | E_p] with E_r[n0][m1][m2] on r-edges (r_c, th_f, ph_f),
+ * E_t[m0][n1][m2] on theta-edges (r_f, th_c, ph_f), E_p[m0][m1][n2] on
+ * phi-edges (r_f, th_f, ph_c), m_a = n_a on a periodic axis, n_a + 1
+ * otherwise (sts_resistivity_sizes).  Face fluxes Phi = C E by Stokes'
+ * theorem (normals +r, +theta, +phi, right-hand rule), energy
+ * 1/2 sum_f (l*_f / S_f) Phi_f^2 (S_f face area, l*_f distance between the
+ * centres of the cells it separates), edge mass H_e = S*_e / L_e (dual-face
+ * area over edge length), all exact for spherical cells:
+ *   F(E) = -eta H^-1 C^T diag(l* / S) C E.
+ * Edges lying in a non-periodic boundary surface keep their values
+ * (tangential E given) and F = 0 there, whatever the scalar boundary kinds.  */
+
+/* sts_set_resistivity - builds the edge / face weight tables for eta > 0
+ * (finite); independent of the scalar operator set by sts_set_*.  */
+sts_status sts_set_resistivity(sts_ctx *ctx, double eta);
+/* sts_resistivity_sizes - sizes[3] = number of E_r, E_t, E_p entries (HOST). */
+sts_status sts_resistivity_sizes(const sts_ctx *ctx, long long sizes[3]);
+/* apply_F_resistivity - FE = F(E), both device FP64 edge vectors, not
+ * overlapping.  */
+sts_status apply_F_resistivity(sts_ctx *ctx, const double *E, double *FE);
+/* resistivity_dt_euler - 2 / (largest Gershgorin row sum of eta H^-1 K over
+ * the interior edges), Appendix B's bound applied to this operator.
+ * Synchronises the stream.  */
+sts_status resistivity_dt_euler(sts_ctx *ctx, double *dt_e);
+/* resistivity_be_pcg_solve - one BE step (H + dt eta C^T W C) E^{n+1} = H E^n
+ * on the interior edges (the fixed edges' terms on the right-hand side) by
+ * the PCG of Fig. "pcg" with PC1.  E_n: E^n (read only).  E: on entry the
+ * initial guess on interior edges (pass a copy of E^n for the paper's
+ * x0 = u^n), on return E^{n+1}, its fixed edges set to E^n's; E must not
+ * alias E_n.  Stops at ||b - A x||_2 <= rtol ||b||_2 over the interior edges
+ * (recursively updated residual) or after maxit iterations; *iters, *relres
+ * as be_pcg_solve.  Returns STS_NOT_CONVERGED at maxit, STS_BREAKDOWN if
+ * p.Ap <= 0.  Synchronises the stream.  */
+sts_status resistivity_be_pcg_solve(sts_ctx *ctx, const double *E_n, double *E, double dt,
+                                    double rtol, int maxit, int *iters, double *relres);
+
 /* sts_be_residual - true relative residual ||b - A x||_2 / ||b||_2 of the BE
  * system above, computed with FP64 dot products.  Synchronises the stream.  */
 sts_status sts_be_residual(sts_ctx *ctx, const double *u_n, const double *x, double dt,

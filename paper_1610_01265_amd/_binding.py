@@ -58,6 +58,11 @@ def load():
         "rkl_step": (I, [P, P, I, D, I, I, I, I, D, D, PI]),
         "apply_F_nonlinear": (I, [P, P, P, D, P, P, P]),
         "rkl2_step_nonlinear": (I, [P, P, D, D, P, P, P, I, PI]),
+        "sts_set_resistivity": (I, [P, D]),
+        "sts_resistivity_sizes": (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
+        "apply_F_resistivity": (I, [P, P, P]),
+        "resistivity_dt_euler": (I, [P, PD]),
+        "resistivity_be_pcg_solve": (I, [P, P, P, D, D, I, PI, PD]),
         "be_pcg_solve": (I, [P, P, P, D, I, PI, D, I, PI, PD]),
         "sts_be_residual": (I, [P, P, P, D, PD]),
         "cnn_create": (I, [ctypes.POINTER(P), P, I, I]),
@@ -86,7 +91,9 @@ def exported_symbols():
     return ["sts_create", "sts_destroy", "sts_set_stream", "sts_last_error", "sts_num_cells",
             "sts_set_spitzer", "sts_set_isotropic", "sts_set_spitzer_f32", "sts_set_isotropic_f32",
             "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "rkl_step",
-            "apply_F_nonlinear", "rkl2_step_nonlinear", "be_pcg_solve",
+            "apply_F_nonlinear", "rkl2_step_nonlinear", "sts_set_resistivity",
+            "sts_resistivity_sizes", "apply_F_resistivity", "resistivity_dt_euler",
+            "resistivity_be_pcg_solve", "be_pcg_solve",
             "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
             "cnn_get_weights", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
             "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_guess"]
@@ -243,6 +250,45 @@ class Context:
             self._h, _ptr(u, n, "u"), float(dt), float(kappa0), _ptr(b0, n, "b0"),
             _ptr(b1, n, "b1"), _ptr(b2, n, "b2"), int(s), ctypes.byref(used)))
         return used.value
+
+    def set_resistivity(self, eta):
+        """Resistive diffusion of A on cell edges (see include/sts.h)."""
+        self._sync_stream()
+        self._check(self._lib.sts_set_resistivity(self._h, float(eta)))
+
+    def resistivity_sizes(self):
+        out = (ctypes.c_longlong * 3)()
+        self._check(self._lib.sts_resistivity_sizes(self._h, out))
+        return tuple(int(v) for v in out)
+
+    def _nedge(self):
+        return sum(self.resistivity_sizes())
+
+    def apply_F_resistivity(self, E, out=None):
+        self._sync_stream()
+        n = self._nedge()
+        if out is None:
+            out = torch.empty_like(E)
+        self._check(self._lib.apply_F_resistivity(self._h, _ptr(E, n, "E"), _ptr(out, n, "out")))
+        return out
+
+    def resistivity_dt_euler(self) -> float:
+        self._sync_stream()
+        v = ctypes.c_double()
+        self._check(self._lib.resistivity_dt_euler(self._h, ctypes.byref(v)))
+        return v.value
+
+    def resistivity_be_pcg_solve(self, E_n, E, dt, rtol=1e-8, maxit=10000,
+                                 allow_not_converged=False):
+        self._sync_stream()
+        n = self._nedge()
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        st = self._lib.resistivity_be_pcg_solve(self._h, _ptr(E_n, n, "E_n"), _ptr(E, n, "E"),
+                                                float(dt), float(rtol), int(maxit),
+                                                ctypes.byref(it), ctypes.byref(rel))
+        self._check(st, (STS_OK, STS_NOT_CONVERGED) if allow_not_converged else (STS_OK,))
+        return it.value, rel.value, st
 
     def be_pcg_solve(self, u_n, x, dt, pc=PC_JACOBI, block=(8, 8, 8), rtol=1e-8, maxit=10000,
                      allow_not_converged=False):

@@ -260,6 +260,23 @@ void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr
                      rtol, maxit);
 }
 
+void launch_init_p_n(const sts_ctx *c, long long n, const double *r, const double *invd,
+                     double *p, double *part, int nparts) {
+  hipLaunchKernelGGL(k_init_p, dim3(nparts), dim3(NT), 0, c->stream, n, r, invd,
+                     (const double *)nullptr, p, part);
+}
+
+void launch_finalize_alpha_n(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, c->stream, part, nparts, sc);
+}
+
+void launch_pass_b_jacobi_n(const sts_ctx *c, long long n, double *x, const double *p, double *r,
+                            const double *y, const double *invd, double *part, int nparts,
+                            const PcgScalars *sc) {
+  hipLaunchKernelGGL(k_pass_b_jac, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y, invd,
+                     part, cap_of(c), sc);
+}
+
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars *sc) {
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, c->stream, part, stencil_parts(c), sc);
 }

@@ -163,6 +163,9 @@ sts_status sts_create(sts_ctx **out, int coord, int n0, int n1, int n2, const do
   ctx->n2 = n2;
   ctx->ncell = ncell;
   std::memcpy(ctx->bc, bc, sizeof(ctx->bc));
+  ctx->hf[0].assign(f0, f0 + n0 + 1);
+  ctx->hf[1].assign(f1, f1 + n1 + 1);
+  ctx->hf[2].assign(f2, f2 + n2 + 1);
   ctx->stream = (hipStream_t)stream;
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     delete ctx;
@@ -279,6 +282,8 @@ sts_status sts_destroy(sts_ctx *ctx) {
   dfree(ctx->d_ilu);
   dfree(ctx->d_flag);
   dfree(ctx->d_tmp);
+  dfree(ctx->d_rtab);
+  dfree(ctx->d_rws);
   if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
   delete ctx;
   return STS_OK;
@@ -898,6 +903,216 @@ sts_status sts_be_residual(sts_ctx *ctx, const double *u_n, const double *x, dou
   HIPCHK(hipStreamSynchronize(ctx->stream));
   *relres = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
   return STS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Resistive diffusion of the vector potential on cell edges (Eq. mhd:a).
+// ---------------------------------------------------------------------------
+namespace {
+
+// centres, centre gaps across each face position, and the centres before /
+// after each face position of one axis (see k_resist.hip for the layout)
+struct AxisGeo {
+  int n, m;
+  std::vector<double> f, c, d, g, cm, cp;
+};
+
+AxisGeo axis_geo(const std::vector<double> &f, bool per) {
+  AxisGeo a;
+  a.n = (int)f.size() - 1;
+  a.m = per ? a.n : a.n + 1;
+  a.f = f;
+  const double P = f[a.n] - f[0];
+  a.c.resize(a.n);
+  a.d.resize(a.n);
+  for (int q = 0; q < a.n; ++q) {
+    a.c[q] = 0.5 * (f[q] + f[q + 1]);
+    a.d[q] = f[q + 1] - f[q];
+  }
+  a.g.assign(a.n + 1, 0.0);
+  for (int q = 1; q < a.n; ++q) a.g[q] = a.c[q] - a.c[q - 1];
+  if (per) a.g[0] = a.g[a.n] = a.c[0] + P - a.c[a.n - 1];
+  a.cm.resize(a.m);
+  a.cp.resize(a.m);
+  for (int q = 0; q < a.m; ++q) {
+    a.cm[q] = q >= 1 ? a.c[q - 1] : (per ? a.c[a.n - 1] - P : f[0]);
+    a.cp[q] = q < a.n ? a.c[q] : f[a.n];
+  }
+  return a;
+}
+
+}  // namespace
+
+sts_status sts_set_resistivity(sts_ctx *ctx, double eta) {
+  if (!ctx) return STS_EINVAL;
+  if (!(eta > 0.0) || !std::isfinite(eta)) FAIL(STS_EINVAL, "eta must be finite and > 0");
+  const bool per[3] = {ctx->bc[0] == STS_BC_PERIODIC, ctx->bc[2] == STS_BC_PERIODIC,
+                       ctx->bc[4] == STS_BC_PERIODIC};
+  const AxisGeo A = axis_geo(ctx->hf[0], per[0]), B = axis_geo(ctx->hf[1], per[1]),
+                C = axis_geo(ctx->hf[2], per[2]);
+  const bool sph = ctx->coord == STS_SPHERICAL;
+  // 18 tables: (H of r-, t-, p-edges, w of r-, t-, p-faces) x (axis 0, 1, 2)
+  std::vector<std::vector<double>> T(18);
+  auto fill = [](int n, auto fn) {
+    std::vector<double> v(n + 1, 0.0);
+    for (int q = 0; q < n; ++q) v[q] = fn(q);
+    return v;
+  };
+  auto half_sq = [](double a, double b) { return 0.5 * (b * b - a * a); };
+  if (sph) {
+    T[0] = fill(A.n, [&](int i) { return A.c[i] * A.c[i] / A.d[i]; });
+    T[1] = fill(B.m, [&](int j) { return std::cos(B.cm[j]) - std::cos(B.cp[j]); });
+    T[2] = fill(C.m, [&](int k) { return C.g[k]; });
+    T[3] = fill(A.m, [&](int i) { return half_sq(A.cm[i], A.cp[i]) / A.f[i]; });
+    T[4] = fill(B.n, [&](int j) { return std::sin(B.c[j]) / B.d[j]; });
+    T[5] = fill(C.m, [&](int k) { return C.g[k]; });
+    T[6] = fill(A.m, [&](int i) { return half_sq(A.cm[i], A.cp[i]) / A.f[i]; });
+    T[7] = fill(B.m, [&](int j) { return (B.cp[j] - B.cm[j]) / std::sin(B.f[j]); });
+    T[8] = fill(C.n, [&](int k) { return 1.0 / C.d[k]; });
+    T[9] = fill(A.m, [&](int i) { return A.g[i] / (A.f[i] * A.f[i]); });
+    T[10] = fill(B.n, [&](int j) { return 1.0 / (std::cos(B.f[j]) - std::cos(B.f[j + 1])); });
+    T[11] = fill(C.n, [&](int k) { return 1.0 / C.d[k]; });
+    T[12] = fill(A.n, [&](int i) { return A.c[i] / half_sq(A.f[i], A.f[i + 1]); });
+    T[13] = fill(B.m, [&](int j) { return B.g[j] / std::sin(B.f[j]); });
+    T[14] = fill(C.n, [&](int k) { return 1.0 / C.d[k]; });
+    T[15] = fill(A.n, [&](int i) { return A.c[i] / half_sq(A.f[i], A.f[i + 1]); });
+    T[16] = fill(B.n, [&](int j) { return std::sin(B.c[j]) / B.d[j]; });
+    T[17] = fill(C.m, [&](int k) { return C.g[k]; });
+  } else {
+    T[0] = fill(A.n, [&](int i) { return 1.0 / A.d[i]; });
+    T[1] = fill(B.m, [&](int j) { return B.g[j]; });
+    T[2] = fill(C.m, [&](int k) { return C.g[k]; });
+    T[3] = fill(A.m, [&](int i) { return A.g[i]; });
+    T[4] = fill(B.n, [&](int j) { return 1.0 / B.d[j]; });
+    T[5] = fill(C.m, [&](int k) { return C.g[k]; });
+    T[6] = fill(A.m, [&](int i) { return A.g[i]; });
+    T[7] = fill(B.m, [&](int j) { return B.g[j]; });
+    T[8] = fill(C.n, [&](int k) { return 1.0 / C.d[k]; });
+    T[9] = fill(A.m, [&](int i) { return A.g[i]; });
+    T[10] = fill(B.n, [&](int j) { return 1.0 / B.d[j]; });
+    T[11] = fill(C.n, [&](int k) { return 1.0 / C.d[k]; });
+    T[12] = fill(A.n, [&](int i) { return 1.0 / A.d[i]; });
+    T[13] = fill(B.m, [&](int j) { return B.g[j]; });
+    T[14] = fill(C.n, [&](int k) { return 1.0 / C.d[k]; });
+    T[15] = fill(A.n, [&](int i) { return 1.0 / A.d[i]; });
+    T[16] = fill(B.n, [&](int j) { return 1.0 / B.d[j]; });
+    T[17] = fill(C.m, [&](int k) { return C.g[k]; });
+  }
+  std::vector<double> flat;
+  for (int t = 0; t < 18; ++t) {
+    ctx->res_off[t] = (int)flat.size();
+    flat.insert(flat.end(), T[t].begin(), T[t].end());
+  }
+  ctx->res_ne[0] = (long long)A.n * B.m * C.m;
+  ctx->res_ne[1] = (long long)A.m * B.n * C.m;
+  ctx->res_ne[2] = (long long)A.m * B.m * C.n;
+  ctx->res_nf[0] = (long long)A.m * B.n * C.n;
+  ctx->res_nf[1] = (long long)A.n * B.m * C.n;
+  ctx->res_nf[2] = (long long)A.n * B.n * C.m;
+  const long long ne = ctx->res_ne[0] + ctx->res_ne[1] + ctx->res_ne[2];
+  const long long nf = ctx->res_nf[0] + ctx->res_nf[1] + ctx->res_nf[2];
+  dfree(ctx->d_rtab);
+  dfree(ctx->d_rws);
+  sts_status st;
+  if ((st = dalloc(ctx, (void **)&ctx->d_rtab, flat.size() * 8)) ||
+      (st = dalloc(ctx, (void **)&ctx->d_rws, (size_t)(2 * nf + 6 * ne) * 8)))
+    return st;
+  HIPCHK(hipMemcpyAsync(ctx->d_rtab, flat.data(), flat.size() * 8, hipMemcpyHostToDevice,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->res_eta = eta;
+  return STS_OK;
+}
+
+sts_status sts_resistivity_sizes(const sts_ctx *ctx, long long sizes[3]) {
+  if (!ctx || !sizes) return STS_EINVAL;
+  const int nn[3] = {ctx->n0, ctx->n1, ctx->n2};
+  int m[3];
+  for (int a = 0; a < 3; ++a) m[a] = nn[a] + (ctx->bc[2 * a] == STS_BC_PERIODIC ? 0 : 1);
+  sizes[0] = (long long)nn[0] * m[1] * m[2];
+  sizes[1] = (long long)m[0] * nn[1] * m[2];
+  sizes[2] = (long long)m[0] * m[1] * nn[2];
+  return STS_OK;
+}
+
+sts_status apply_F_resistivity(sts_ctx *ctx, const double *E, double *FE) {
+  if (!ctx) return STS_EINVAL;
+  if (!(ctx->res_eta > 0.0)) FAIL(STS_EINVAL, "resistivity not set (sts_set_resistivity)");
+  if (!E || !FE || E == FE) FAIL(STS_EINVAL, "apply_F_resistivity: null or aliased arrays");
+  launch_res_F(ctx, E, ctx->d_rws, FE);
+  LAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status resistivity_dt_euler(sts_ctx *ctx, double *dt_e) {
+  if (!ctx || !dt_e) return STS_EINVAL;
+  if (!(ctx->res_eta > 0.0)) FAIL(STS_EINVAL, "resistivity not set (sts_set_resistivity)");
+  const int np = res_parts(ctx);
+  sts_status st;
+  if ((st = ensure_red(ctx, np))) return st;
+  launch_res_gershgorin(ctx, ctx->d_rws, ctx->d_red);
+  LAUNCHCHK();
+  std::vector<double> h(np);
+  HIPCHK(hipMemcpyAsync(h.data(), ctx->d_red, (size_t)np * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double m = 0.0;
+  for (double v : h) m = std::max(m, v);
+  if (!(m > 0.0) || !std::isfinite(m)) FAIL(STS_EINVAL, "no interior edges");
+  *dt_e = 2.0 / m;
+  return STS_OK;
+}
+
+sts_status resistivity_be_pcg_solve(sts_ctx *ctx, const double *E_n, double *E, double dt,
+                                    double rtol, int maxit, int *iters, double *relres) {
+  if (!ctx) return STS_EINVAL;
+  if (!(ctx->res_eta > 0.0)) FAIL(STS_EINVAL, "resistivity not set (sts_set_resistivity)");
+  if (!E_n || !E || E_n == E) FAIL(STS_EINVAL, "resistivity_be_pcg_solve: null or aliased arrays");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "dt must be finite, > 0");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol)) FAIL(STS_EINVAL, "bad rtol");
+  if (maxit < 0) FAIL(STS_EINVAL, "maxit must be >= 0");
+  const int P = res_parts(ctx);
+  sts_status st;
+  if ((st = ensure_red(ctx, std::max(P, pcg_parts(ctx))))) return st;
+  if ((st = dalloc(ctx, (void **)&ctx->d_sc, sizeof(PcgScalars)))) return st;
+  const long long ne = ctx->res_ne[0] + ctx->res_ne[1] + ctx->res_ne[2];
+  const long long nf = ctx->res_nf[0] + ctx->res_nf[1] + ctx->res_nf[2];
+  const long long cap = ctx->red_cap;
+  double *Phi = ctx->d_rws, *Wf = Phi + nf, *b = Phi + 2 * nf, *invd = b + ne, *r = b + 2 * ne,
+         *p0 = b + 3 * ne, *p1 = b + 4 * ne, *y = b + 5 * ne;
+  double *part = ctx->d_red;
+  PcgScalars *sc = ctx->d_sc;
+  launch_res_rhs(ctx, E_n, dt, E, b, invd, Phi, Wf, part + 2 * cap);
+  LAUNCHCHK();
+  launch_res_residual(ctx, b, E, dt, Phi, r, part + cap);
+  LAUNCHCHK();
+  launch_init_p_n(ctx, ne, r, invd, p0, part, P);
+  LAUNCHCHK();
+  launch_finalize_init_n(ctx, part + 2 * cap, P, part + cap, P, part, P, sc, rtol, maxit);
+  LAUNCHCHK();
+  PcgScalars *h = (PcgScalars *)ctx->h_pin;
+  double *pold = p0, *pnew = p1;
+  HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int it = 0; it < maxit && !h->done; ++it) {
+    launch_res_pass_a(ctx, dt, r, invd, pold, pnew, Phi, y, part, sc, it == 0);
+    launch_finalize_alpha_n(ctx, part, P, sc);
+    launch_pass_b_jacobi_n(ctx, ne, E, pnew, r, y, invd, part, P, sc);
+    launch_finalize_beta(ctx, part, P, sc);
+    LAUNCHCHK();
+    std::swap(pold, pnew);
+    if ((it + 1) % kPollEvery == 0 || it + 1 == maxit) {
+      HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+  }
+  HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (iters) *iters = h->iters;
+  if (relres) *relres = h->bnorm2 > 0 ? std::sqrt(h->rnorm2 / h->bnorm2) : 0.0;
+  if (h->status == -4) FAIL(STS_BREAKDOWN, "PCG breakdown: p.Ap <= 0 or non-finite residual");
+  if (h->status == 1) return STS_OK;
+  ctx->err = "PCG reached maxit";
+  return STS_NOT_CONVERGED;
 }
 
 }  // extern "C"

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/sts.h"
 
@@ -104,6 +105,14 @@ struct sts_ctx {
   long long ilu_cap = 0;
   int *d_flag = nullptr;      // device flags (input checks, ILU breakdown)
   double *d_tmp = nullptr;    // small device scratch for host-read scalars
+
+  // resistive diffusion of A on cell edges (set by sts_set_resistivity)
+  std::vector<double> hf[3];  // face coordinates (host copy)
+  double res_eta = 0.0;       // 0: not set
+  long long res_ne[3] = {0, 0, 0}, res_nf[3] = {0, 0, 0};  // edges / faces per component
+  int res_off[18] = {};       // offsets of the 18 weight tables in d_rtab
+  double *d_rtab = nullptr;
+  double *d_rws = nullptr;    // faces x 2, edges x 6 (PCG vectors)
   void *h_pin = nullptr;      // pinned host mirror of flags / scalars
 
   sts::Grid grid() const;
@@ -143,6 +152,25 @@ void launch_stage_nl(const sts_ctx *c, int mode, const double *ukm1, const doubl
                      const double *u0, double *F0, double *out, double mu, double nu,
                      double mut_dt, double gt_dt, double kappa0, const double *b0,
                      const double *b1, const double *b2);
+
+// Resistive diffusion on edges (k_resist.hip).  Phi / Wf: face-sized scratch.
+int res_parts(const sts_ctx *c);
+void launch_res_F(const sts_ctx *c, const double *E, double *Phi, double *FE);
+void launch_res_gershgorin(const sts_ctx *c, double *Phi, double *part);
+void launch_res_rhs(const sts_ctx *c, const double *En, double dt, double *x, double *b,
+                    double *invd, double *Phi, double *Wf, double *part);
+void launch_res_residual(const sts_ctx *c, const double *b, const double *x, double dt,
+                         double *Phi, double *r, double *part);
+void launch_res_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
+                       const double *pold, double *p, double *Phi, double *y, double *part,
+                       const PcgScalars *sc, int first);
+// PCG pieces over a vector of n entries (k_pcg.hip)
+void launch_init_p_n(const sts_ctx *c, long long n, const double *r, const double *invd,
+                     double *p, double *part, int nparts);
+void launch_finalize_alpha_n(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
+void launch_pass_b_jacobi_n(const sts_ctx *c, long long n, double *x, const double *p, double *r,
+                            const double *y, const double *invd, double *part, int nparts,
+                            const PcgScalars *sc);
 
 // FP32 form (k_stencil.hip, k_pcg.hip)
 void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1, double mut_dt);

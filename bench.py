@@ -16,7 +16,9 @@ One step = one pass of the whole path over the synthetic shell input:
     sub-cycles, explicit Euler over a quarter step then RKL2, and RKL1 with
     one extra stage;
   * RKL2 with the diffusivity taken from every stage value (no lagging):
-    one rkl2_step_nonlinear (its own set-up at u^n included).
+    one rkl2_step_nonlinear (its own set-up at u^n included);
+  * resistive diffusion of the edge-staggered vector potential (Eq. mhd:a):
+    one BE step by PC1-PCG at dt = f x its own explicit limit.
 Inputs are resident in HBM before the timed region.  Each phase is bracketed
 by HIP events on the library's stream.  `value` is the RKL2 throughput in
 cell-stage updates per second; the BE solve times are reported beside it.
@@ -54,7 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="shell128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phases", default="rkl2,jacobi,ilu0,fp32,visc,learned,variants,nonlinear",
+    ap.add_argument("--phases",
+                    default="rkl2,jacobi,ilu0,fp32,visc,learned,variants,nonlinear,resist",
                     help="comma list of timed phases (profiling runs)")
     ap.add_argument("--learned-train-seeds", type=int, default=24,
                     help="training pairs (seeds 1..N) for the network before the timed steps")
@@ -154,6 +157,31 @@ def nonlinear_entry(ph, info, ncell):
                              "frac_hbm": gbs / HBM_PEAK_GBS if gbs else None}}
 
 
+RES_ETA = 1.0  # c^2 eta / 4 pi in code units (it cancels in dt / dt_Euler)
+
+
+def resist_entry(ph, info, ctxr):
+    """BE + PC1 of the resistive term: time, iterations, and per iteration the
+    HBM bytes the five sweeps move at minimum (RES_BYTES_PER_EDGE per edge)
+    over the mean iteration time."""
+    it = info.get("it_resist")
+    if not it or ctxr is None:
+        return None
+    ne = sum(ctxr.resistivity_sizes())
+    t = ph["resist_be"]
+    per_it = t / it * 1e3  # us (set-up included)
+    gbs = RES_BYTES_PER_EDGE * ne / (per_it * 1e-6) / 1e9
+    return {"ms": t, "iterations": it, "edges": ne, "us_per_iteration": per_it,
+            "alg_bytes_per_edge_iteration": RES_BYTES_PER_EDGE, "achieved_GBs": gbs,
+            "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
+# p = z + beta p (r, 1/diag, p_old in, p out: 32 B), face fluxes (p in, w C p
+# out: 16 B), C^T + matvec (fluxes, p in, y out: 24 B), pass B (x, p, r, y,
+# 1/diag in; x, r out: 56 B) -- per edge, faces counted as one per edge.
+RES_BYTES_PER_EDGE = 128
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -164,7 +192,7 @@ def main():
     import torch
     import paper_1610_01265_amd as sts
     from paper_1610_01265_amd import learned
-    from workloads import WORKLOADS, flatten, he_normal, make_workload
+    from workloads import WORKLOADS, edge_potential, flatten, he_normal, make_workload
 
     wl = WORKLOADS[args.workload]
     w = make_workload(wl, with_velocity=True)
@@ -189,6 +217,14 @@ def main():
     xv = torch.empty_like(T)
     ncell = T.numel()
     stream = torch.cuda.current_stream()
+
+    ctxr = None
+    if "resist" in phases:
+        # tables are constant for a grid: set once, outside the timed steps
+        ctxr = shell_ctx(0.0)
+        ctxr.set_resistivity(RES_ETA)
+        E0 = dev(edge_potential(wl.nr, wl.nth, wl.nph))
+        Ex = torch.empty_like(E0)
 
     net = None
     held = None
@@ -290,6 +326,11 @@ def main():
         if "nonlinear" in phases:
             u.copy_(T)
             info["s_nl"] = ctx.rkl2_step_nonlinear(u, dt, w["kappa0"], br, bt, bp)
+        tm.mark("resist_be")
+        if "resist" in phases:
+            dtr = wl.dt_factor * ctxr.resistivity_dt_euler()
+            Ex.copy_(E0)
+            info["it_resist"], _, _ = ctxr.resistivity_be_pcg_solve(E0, Ex, dtr, rtol=wl.rtol)
         tm.mark("end")
         if rec is not None:
             rec.append((tm, info))
@@ -362,6 +403,7 @@ def main():
             "rkl1_one_extra_stage": {"ms": ph.get("var_rkl1_extra1"),
                                      "operator_applications": info.get("n_rkl1")}},
         "nonlinear_kappa_rkl2": nonlinear_entry(ph, info, ncell),
+        "resistivity_be_pc1": resist_entry(ph, info, ctxr),
         "learned": dict(learned_info, guess_used_net=info.get("guess_used_net"),
                         guess_relres_net_prev=info.get("guess_relres"),
                         train_step_ms=ph.get("learned_train")),
@@ -376,7 +418,7 @@ def main():
     print(json.dumps(out), flush=True)
     if net is not None:
         net.close()
-    for c in (ctx, ctx32, ctxv):
+    for c in (ctx, ctx32, ctxv) + ((ctxr,) if ctxr is not None else ()):
         c.close()
 
 

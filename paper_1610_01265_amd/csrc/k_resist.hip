@@ -29,7 +29,7 @@ namespace sts {
 
 namespace {
 
-constexpr int RT = 256;
+constexpr int RX = 64, RY = 4, RT = RX * RY;
 
 struct RDims {
   int n0, n1, n2, m0, m1, m2, per0, per1, per2;
@@ -82,13 +82,17 @@ enum { RK_FLUX = 0, RK_COUNT = 1, RK_WEIGHT = 2 };
 template <int MASK, int KIND>
 __global__ void __launch_bounds__(RT) k_rcurl(RDims d, const double *__restrict__ E,
                                               double *__restrict__ Phi) {
-  const long long tot = d.nf[0] + d.nf[1] + d.nf[2];
-  for (long long q = (long long)blockIdx.x * RT + threadIdx.x; q < tot;
-       q += (long long)gridDim.x * RT) {
+  // threads: phi index across lanes, theta across threads / blocks; the
+  // workgroup strides over the r-planes of the three face arrays
+  const int k = blockIdx.x * RX + threadIdx.x, j = blockIdx.y * RY + threadIdx.y;
+  const int zt = d.m0 + 2 * d.n0;
+  for (int z = blockIdx.z; z < zt; z += gridDim.z) {
     double phi, w;
-    if (q < d.nf[0]) {  // r-face (i < m0, j < n1, k < n2)
-      const long long s = q;
-      const int k = (int)(s % d.n2), j = (int)((s / d.n2) % d.n1), i = (int)(s / ((long long)d.n2 * d.n1));
+    long long q;
+    if (z < d.m0) {  // r-face (i < m0, j < n1, k < n2)
+      const int i = z;
+      if (j >= d.n1 || k >= d.n2) continue;
+      q = ((long long)i * d.n1 + j) * d.n2 + k;
       const int kp = nxt(k, d.n2, d.per2), jp = nxt(j, d.n1, d.per1);
       const bool f1 = fixed_t(d, i, k), f2 = fixed_p(d, i, jp), f3 = fixed_t(d, i, kp),
                  f4 = fixed_p(d, i, j);
@@ -100,9 +104,10 @@ __global__ void __launch_bounds__(RT) k_rcurl(RDims d, const double *__restrict_
         phi = ev<MASK>(E, it(d, i, j, k), f1) + ev<MASK>(E, ip(d, i, jp, k), f2) -
               ev<MASK>(E, it(d, i, j, kp), f3) - ev<MASK>(E, ip(d, i, j, k), f4);
       w = tb(d, R_W, i) * tb(d, R_W + 1, j) * tb(d, R_W + 2, k);
-    } else if (q < d.nf[0] + d.nf[1]) {  // t-face (i < n0, j < m1, k < n2)
-      const long long s = q - d.nf[0];
-      const int k = (int)(s % d.n2), j = (int)((s / d.n2) % d.m1), i = (int)(s / ((long long)d.n2 * d.m1));
+    } else if (z < d.m0 + d.n0) {  // t-face (i < n0, j < m1, k < n2)
+      const int i = z - d.m0;
+      if (j >= d.m1 || k >= d.n2) continue;
+      q = d.nf[0] + ((long long)i * d.m1 + j) * d.n2 + k;
       const int kp = nxt(k, d.n2, d.per2), iq = nxt(i, d.n0, d.per0);
       const bool f1 = fixed_r(d, j, kp), f2 = fixed_r(d, j, k), f3 = fixed_p(d, iq, j),
                  f4 = fixed_p(d, i, j);
@@ -115,8 +120,9 @@ __global__ void __launch_bounds__(RT) k_rcurl(RDims d, const double *__restrict_
               ev<MASK>(E, ip(d, iq, j, k), f3) + ev<MASK>(E, ip(d, i, j, k), f4);
       w = tb(d, T_W, i) * tb(d, T_W + 1, j) * tb(d, T_W + 2, k);
     } else {  // p-face (i < n0, j < n1, k < m2)
-      const long long s = q - d.nf[0] - d.nf[1];
-      const int k = (int)(s % d.m2), j = (int)((s / d.m2) % d.n1), i = (int)(s / ((long long)d.m2 * d.n1));
+      const int i = z - d.m0 - d.n0;
+      if (j >= d.n1 || k >= d.m2) continue;
+      q = d.nf[0] + d.nf[1] + ((long long)i * d.n1 + j) * d.m2 + k;
       const int iq = nxt(i, d.n0, d.per0), jq = nxt(j, d.n1, d.per1);
       const bool f1 = fixed_t(d, iq, k), f2 = fixed_t(d, i, k), f3 = fixed_r(d, jq, k),
                  f4 = fixed_r(d, j, k);
@@ -150,16 +156,19 @@ struct RArgs {
 template <int MODE>
 __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict__ Phi,
                                                const double *__restrict__ Wf, RArgs a) {
-  const long long tot = d.ne[0] + d.ne[1] + d.ne[2];
   const double *Fr = Phi, *Ft = Phi + d.nf[0], *Fp = Phi + d.nf[0] + d.nf[1];
   double acc1 = 0.0, acc2 = 0.0;
-  for (long long e = (long long)blockIdx.x * RT + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * RT) {
+  const int k = blockIdx.x * RX + threadIdx.x, j = blockIdx.y * RY + threadIdx.y;
+  const int zt = d.n0 + 2 * d.m0;
+  for (int z = blockIdx.z; z < zt; z += gridDim.z) {
     bool fixed;
     double s = 0.0, h, wsum = 0.0;
+    long long e;
     // faces of the edge: (flux index, sign) x 4
-    if (e < d.ne[0]) {  // r-edge (i < n0, j < m1, k < m2)
-      const int k = (int)(e % d.m2), j = (int)((e / d.m2) % d.m1), i = (int)(e / ((long long)d.m2 * d.m1));
+    if (z < d.n0) {  // r-edge (i < n0, j < m1, k < m2)
+      const int i = z;
+      if (j >= d.m1 || k >= d.m2) continue;
+      e = ((long long)i * d.m1 + j) * d.m2 + k;
       fixed = fixed_r(d, j, k);
       h = tb(d, R_H, i) * tb(d, R_H + 1, j) * tb(d, R_H + 2, k);
       if (!fixed) {
@@ -174,9 +183,10 @@ __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict
         }
         if (MODE != RC_GERSH) s = -Ft[t0 + k] + Ft[t0 + km] + Fp[p0 + k] - Fp[p1 + k];
       }
-    } else if (e < d.ne[0] + d.ne[1]) {  // t-edge (i < m0, j < n1, k < m2)
-      const long long x = e - d.ne[0];
-      const int k = (int)(x % d.m2), j = (int)((x / d.m2) % d.n1), i = (int)(x / ((long long)d.m2 * d.n1));
+    } else if (z < d.n0 + d.m0) {  // t-edge (i < m0, j < n1, k < m2)
+      const int i = z - d.n0;
+      if (j >= d.n1 || k >= d.m2) continue;
+      e = d.ne[0] + ((long long)i * d.n1 + j) * d.m2 + k;
       fixed = fixed_t(d, i, k);
       h = tb(d, T_H, i) * tb(d, T_H + 1, j) * tb(d, T_H + 2, k);
       if (!fixed) {
@@ -192,8 +202,9 @@ __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict
         if (MODE != RC_GERSH) s = Fr[r0 + k] - Fr[r0 + km] - Fp[p0 + k] + Fp[p1 + k];
       }
     } else {  // p-edge (i < m0, j < m1, k < n2)
-      const long long x = e - d.ne[0] - d.ne[1];
-      const int k = (int)(x % d.n2), j = (int)((x / d.n2) % d.m1), i = (int)(x / ((long long)d.n2 * d.m1));
+      const int i = z - d.n0 - d.m0;
+      if (j >= d.m1 || k >= d.n2) continue;
+      e = d.ne[0] + d.ne[1] + ((long long)i * d.m1 + j) * d.n2 + k;
       fixed = fixed_p(d, i, j);
       h = tb(d, P_H, i) * tb(d, P_H + 1, j) * tb(d, P_H + 2, k);
       if (!fixed) {
@@ -232,17 +243,19 @@ __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict
       if (!fixed) acc1 = fmax(acc1, a.eta * wsum / h);
     }
   }
+  const int tid = threadIdx.y * RX + threadIdx.x;
+  const int wg = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   if (MODE == RC_GERSH) {
     __shared__ double red[RT];
-    red[threadIdx.x] = acc1;
+    red[tid] = acc1;
     __syncthreads();
     for (int hh = RT / 2; hh > 0; hh >>= 1) {
-      if (threadIdx.x < hh) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + hh]);
+      if (tid < hh) red[tid] = fmax(red[tid], red[tid + hh]);
       __syncthreads();
     }
-    if (threadIdx.x == 0) a.part[blockIdx.x] = red[0];
+    if (tid == 0) a.part[wg] = red[0];
   } else if (MODE != RC_F) {
-    wg_sum2<RT>(acc1, acc2, threadIdx.x, a.part + blockIdx.x, nullptr);
+    wg_sum2<RT>(acc1, acc2, tid, a.part + wg, nullptr);
   }
 }
 
@@ -258,18 +271,33 @@ __global__ void __launch_bounds__(RT)
     p[e] = r[e] * invd[e] + (first ? 0.0 : beta * pold[e]);
 }
 
+// 3D launch: x over phi, y over theta, z strides over the r-planes of the
+// three arrays (about 2048 workgroups)
+dim3 grid3r(const sts_ctx *c, int zt) {
+  const int gx = (c->n2 + 1 + RX - 1) / RX, gy = (c->n1 + 1 + RY - 1) / RY;
+  const int gz = std::max(1, std::min(zt, 2048 / std::max(1, gx * gy)));
+  return dim3(gx, gy, gz);
+}
+
+int zt_faces(const sts_ctx *c) {
+  return (c->n0 + (c->bc[0] == STS_BC_PERIODIC ? 0 : 1)) + 2 * c->n0;
+}
+int zt_edges(const sts_ctx *c) {
+  return c->n0 + 2 * (c->n0 + (c->bc[0] == STS_BC_PERIODIC ? 0 : 1));
+}
+
 template <int MASK, int KIND>
 void curl_launch(const sts_ctx *c, const RDims &d, const double *E, double *Phi) {
-  const long long tot = d.nf[0] + d.nf[1] + d.nf[2];
-  const int g = (int)std::min<long long>((tot + RT - 1) / RT, 4096);
-  hipLaunchKernelGGL((k_rcurl<MASK, KIND>), dim3(g), dim3(RT), 0, c->stream, d, E, Phi);
+  hipLaunchKernelGGL((k_rcurl<MASK, KIND>), grid3r(c, zt_faces(c)), dim3(RX, RY), 0, c->stream,
+                     d, E, Phi);
 }
 
 }  // namespace
 
+// workgroups of the edge sweep (its partial sums), also the 1D grids' size
 int res_parts(const sts_ctx *c) {
-  const long long tot = c->res_ne[0] + c->res_ne[1] + c->res_ne[2];
-  return (int)std::min<long long>((tot + RT - 1) / RT, 2048);
+  const dim3 g = grid3r(c, zt_edges(c));
+  return (int)(g.x * g.y * g.z);
 }
 
 static RDims rdims(const sts_ctx *c) {
@@ -295,7 +323,8 @@ static RDims rdims(const sts_ctx *c) {
 template <int MODE>
 static void curlT_launch(const sts_ctx *c, const RDims &d, const double *Phi, const double *Wf,
                          const RArgs &a) {
-  hipLaunchKernelGGL(k_rcurlT<MODE>, dim3(res_parts(c)), dim3(RT), 0, c->stream, d, Phi, Wf, a);
+  hipLaunchKernelGGL(k_rcurlT<MODE>, grid3r(c, zt_edges(c)), dim3(RX, RY), 0, c->stream, d, Phi,
+                     Wf, a);
 }
 
 void launch_res_F(const sts_ctx *c, const double *E, double *Phi, double *FE) {

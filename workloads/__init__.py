@@ -18,5 +18,6 @@ from .shell import (  # noqa: F401
     velocity,
     make_workload,
     random_unit_vectors,
+    edge_potential,
 )
 from .cnn_init import he_normal, flatten, unflatten, layer_dims  # noqa: F401,E402

@@ -119,6 +119,15 @@ def velocity(rf, thf, phf, seeds=(1, 2, 3)):
     return tuple(smooth_noise((nr, nth, nph), s) for s in seeds)
 
 
+def edge_potential(nr: int, nth: int, nph: int, seed: int = 4):
+    """A seeded vector-potential field on the cell edges of an nr x nth x nph
+    shell (phi periodic), in the edge layout [E_r | E_t | E_p] with E_r
+    [nr][nth+1][nph], E_t [nr+1][nth][nph], E_p [nr+1][nth+1][nph]: smooth
+    noise per component (inputs only; no arithmetic of the method)."""
+    shapes = ((nr, nth + 1, nph), (nr + 1, nth, nph), (nr + 1, nth + 1, nph))
+    return np.concatenate([smooth_noise(s, seed + q).ravel() for q, s in enumerate(shapes)])
+
+
 @dataclasses.dataclass(frozen=True)
 class Workload:
     """One named synthetic workload (the shapes of the paper-style configs)."""

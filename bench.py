@@ -19,7 +19,10 @@ One step = one pass of the whole path over the synthetic shell input:
     one rkl2_step_nonlinear (its own set-up at u^n included);
   * resistive diffusion of the edge-staggered vector potential (Eq. mhd:a):
     one BE step by PC1-PCG at dt = f x its own explicit limit.
-Inputs are resident in HBM before the timed region.  Each phase is bracketed
+Inputs are resident in HBM before the timed region.  After the timed steps,
+a march of 10 successive steps per method (RKL2, Jacobi-PCG, block-ILU0-PCG)
+re-freezes kappa from each method's evolving state at every step and reports
+per-step times, stage counts and iteration counts ("successive_steps").  Each phase is bracketed
 by HIP events on the library's stream.  `value` is the RKL2 throughput in
 cell-stage updates per second; the BE solve times are reported beside it.
 
@@ -59,6 +62,9 @@ def parse():
     ap.add_argument("--phases",
                     default="rkl2,jacobi,ilu0,fp32,visc,learned,variants,nonlinear,resist",
                     help="comma list of timed phases (profiling runs)")
+    ap.add_argument("--march-steps", type=int, default=10,
+                    help="successive steps per method in the march run after the timed steps "
+                         "(0 skips it)")
     ap.add_argument("--learned-train-seeds", type=int, default=24,
                     help="training pairs (seeds 1..N) for the network before the timed steps")
     ap.add_argument("--learned-epochs", type=int, default=3)
@@ -134,6 +140,43 @@ class Timer:
         for (a, ea), (_, eb) in zip(self.marks, self.marks[1:]):
             out[a] = out.get(a, 0.0) + ea.elapsed_time(eb)
         return out  # ms
+
+
+def run_march(torch, sts, ctx, T, b, kappa0, wl, nsteps, stream):
+    """The lagged protocol over nsteps successive steps: each method marches
+    its own state from T, re-freezing kappa from that state at the start of
+    every step; dt stays at f x the first step's dt_Euler and the RKL2 stage
+    count follows each step's own dt_Euler.  Per-step times (set-up included)
+    come from HIP events on the library's stream."""
+    ctx.set_spitzer(T, kappa0, *b)
+    dt = wl.dt_factor * ctx.dt_euler()
+    ua, ub = torch.empty_like(T), torch.empty_like(T)
+    out = {"steps": nsteps, "dt_over_first_dt_euler": wl.dt_factor}
+    for name in ("rkl2", "jacobi", "ilu0"):
+        ua.copy_(T)
+        evs, work = [], []
+        for _ in range(nsteps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.set_spitzer(ua, kappa0, *b)
+            if name == "rkl2":
+                work.append(ctx.rkl2_step(ua, dt))
+            else:
+                ub.copy_(ua)
+                pc = sts.PC_JACOBI if name == "jacobi" else sts.PC_BLOCK_ILU0
+                it, _, _ = ctx.be_pcg_solve(ua, ub, dt, pc=pc, block=wl.block, rtol=wl.rtol)
+                work.append(it)
+                ua, ub = ub, ua
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(z) for a, z in evs]
+        out[name] = {"ms_per_step": ms, "mean_ms": sum(ms) / nsteps,
+                     ("stages" if name == "rkl2" else "iters"): work}
+    out["speedup_vs_fp64_jacobi_pcg"] = {
+        k: out["jacobi"]["mean_ms"] / out[k]["mean_ms"] for k in ("rkl2", "ilu0")}
+    return out
 
 
 def nonlinear_entry(ph, info, ncell):
@@ -344,6 +387,10 @@ def main():
         step(recs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    march = None
+    if args.march_steps > 0:
+        march = run_march(torch, sts, ctx, T, (br, bt, bp), w["kappa0"], wl, args.march_steps,
+                          stream)
     ph = {}
     for tm, _ in recs:
         for k, val in tm.intervals().items():
@@ -395,6 +442,7 @@ def main():
             "learned_guess_jacobi": ratio(t_jac, t_learn),
             "rkl2_step": ratio(t_jac, t_rk),
             "fp32_form_rkl2_step": ratio(t_jac, sec["fp32_rkl2"])},
+        "successive_steps": march,
         "super_step_variants": {
             "rkl2_10_subcycles": {"ms": ph.get("var_subcycle10"),
                                   "operator_applications": info.get("n_sub10")},

@@ -42,9 +42,11 @@ __device__ __forceinline__ Nb nbr(int i, int n, int per) {
 }
 
 // Operands the FP64 RKL2 stage reads or writes once per sweep (u_{k-2}, u_0,
-// F0, u_k) are accessed non-temporally, leaving the caches to the halo and
-// neighbour-coefficient re-reads (STS_NT=0 turns this off).  Measured per
-// kernel: the FP32 stages and the PCG sweeps ran slower this way.
+// F0, u_k), and the own-cell coefficients and outputs (p, A p) of the FP64
+// conduction PCG pass A, are accessed non-temporally, leaving the caches to
+// the halo and neighbour-coefficient re-reads (STS_NT=0 turns this off).
+// Measured per kernel: the FP32 stages, the viscosity pass A and the
+// element-wise PCG pass B ran slower this way.
 #ifndef STS_NT
 #define STS_NT 1
 #endif

@@ -45,14 +45,17 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-// p = z (z = invd r for Jacobi, or the given z); partial sums r . z
+// p = z (z = invd r for Jacobi, or the given z); partial sums r . z.
+// zout (may be null) receives the Jacobi z.
 __global__ void __launch_bounds__(NT)
     k_init_p(long long n, const double *__restrict__ r, const double *__restrict__ invd,
-             const double *__restrict__ zilu, double *__restrict__ p, double *part) {
+             const double *__restrict__ zilu, double *__restrict__ p, double *part,
+             double *__restrict__ zout) {
   double rz = 0.0;
   const long long stride = (long long)gridDim.x * NT;
   for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
-    const double z = zilu ? zilu[c] : invd[c] * r[c];
+    const double z = zilu ? zilu[c] : r[c] * invd[c];
+    if (zout) zout[c] = z;
     p[c] = z;
     rz += r[c] * z;
   }
@@ -114,8 +117,8 @@ __global__ void k_fin_alpha(const double *part, int n, PcgScalars *sc) {
 __global__ void __launch_bounds__(NT)
     k_pass_b_jac(long long n, double *__restrict__ x, const double *__restrict__ p,
                  double *__restrict__ r, const double *__restrict__ y,
-                 const double *__restrict__ invd, double *part, long long cap,
-                 const PcgScalars *sc) {
+                 const double *__restrict__ invd, double *__restrict__ zout, double *part,
+                 long long cap, const PcgScalars *sc) {
   if (sc->done) return;
   const double alpha = sc->alpha;
   double rz = 0.0, rr = 0.0;
@@ -124,7 +127,11 @@ __global__ void __launch_bounds__(NT)
     x[c] = x[c] + alpha * p[c];
     const double rn = r[c] - alpha * y[c];
     r[c] = rn;
-    rz += rn * (rn * invd[c]);
+    const double zn = rn * invd[c];
+    // the stored z lets the next pass A read two arrays per halo plane
+    // (z, p) instead of three (r, 1/A_ii, p)
+    if (zout) zout[c] = zn;
+    rz += rn * zn;
     rr += rn * rn;
   }
   wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
@@ -159,7 +166,7 @@ __global__ void k_fin_beta(const double *part, int n, long long cap, PcgScalars 
 __global__ void __launch_bounds__(NT)
     k_f32_init(long long n, const double *__restrict__ r64, const double *__restrict__ invd64,
                float *__restrict__ r, float *__restrict__ invd, float *__restrict__ e,
-               double *part, long long cap) {
+               float *__restrict__ z, double *part, long long cap) {
   double rz = 0.0, rr = 0.0;
   const long long stride = (long long)gridDim.x * NT;
   for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
@@ -167,7 +174,9 @@ __global__ void __launch_bounds__(NT)
     r[c] = rv;
     invd[c] = iv;
     e[c] = 0.0f;
-    rz += (double)rv * (double)(rv * iv);
+    const float zv = rv * iv;
+    z[c] = zv;
+    rz += (double)rv * (double)zv;
     rr += (double)rv * (double)rv;
   }
   wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
@@ -176,8 +185,8 @@ __global__ void __launch_bounds__(NT)
 __global__ void __launch_bounds__(NT)
     k_f32_pass_b(long long n, float *__restrict__ e, const float *__restrict__ p,
                  float *__restrict__ r, const float *__restrict__ y,
-                 const float *__restrict__ invd, double *part, long long cap,
-                 const PcgScalars *sc) {
+                 const float *__restrict__ invd, float *__restrict__ z, double *part,
+                 long long cap, const PcgScalars *sc) {
   if (sc->done) return;
   const float alpha = (float)sc->alpha;
   double rz = 0.0, rr = 0.0;
@@ -186,7 +195,9 @@ __global__ void __launch_bounds__(NT)
     e[c] = e[c] + alpha * p[c];
     const float rn = r[c] - alpha * y[c];
     r[c] = rn;
-    rz += (double)rn * (double)(rn * invd[c]);
+    const float zn = rn * invd[c];
+    z[c] = zn;
+    rz += (double)rn * (double)zn;
     rr += (double)rn * (double)rn;
   }
   wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
@@ -239,10 +250,10 @@ void launch_be_rhs(const sts_ctx *c, const double *u_n, double dt, double *b, do
 }
 
 void launch_init_p(const sts_ctx *c, const double *r, const double *invd, const double *zilu,
-                   double *p, double *part) {
+                   double *p, double *part, double *zout) {
   const long long n = c->ncell;
   hipLaunchKernelGGL(k_init_p, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, n,
-                     r, invd, zilu, p, part);
+                     r, invd, zilu, p, part, zout);
 }
 
 void launch_finalize_init_n(const sts_ctx *c, const double *pb, int nb, const double *prr,
@@ -263,7 +274,7 @@ void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr
 void launch_init_p_n(const sts_ctx *c, long long n, const double *r, const double *invd,
                      double *p, double *part, int nparts) {
   hipLaunchKernelGGL(k_init_p, dim3(nparts), dim3(NT), 0, c->stream, n, r, invd,
-                     (const double *)nullptr, p, part);
+                     (const double *)nullptr, p, part, (double *)nullptr);
 }
 
 void launch_finalize_alpha_n(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc) {
@@ -274,7 +285,7 @@ void launch_pass_b_jacobi_n(const sts_ctx *c, long long n, double *x, const doub
                             const double *y, const double *invd, double *part, int nparts,
                             const PcgScalars *sc) {
   hipLaunchKernelGGL(k_pass_b_jac, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y, invd,
-                     part, cap_of(c), sc);
+                     (double *)nullptr, part, cap_of(c), sc);
 }
 
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars *sc) {
@@ -282,10 +293,10 @@ void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars
 }
 
 void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
-                          const double *y, const double *invd, double *part,
+                          const double *y, const double *invd, double *z, double *part,
                           const PcgScalars *sc) {
   hipLaunchKernelGGL(k_pass_b_jac, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, x, p,
-                     r, y, invd, part, cap_of(c), sc);
+                     r, y, invd, z, part, cap_of(c), sc);
 }
 
 void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc) {
@@ -307,15 +318,15 @@ void launch_sum2(const sts_ctx *c, const double *part, int nparts, double *out2)
 namespace sts {
 
 void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, float *r,
-                    float *invd, float *e, double *part) {
+                    float *invd, float *e, float *z, double *part) {
   hipLaunchKernelGGL(k_f32_init, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, r64,
-                     invd64, r, invd, e, part, (long long)c->red_cap);
+                     invd64, r, invd, e, z, part, (long long)c->red_cap);
 }
 
 void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const float *y,
-                const float *invd, double *part, const PcgScalars *sc) {
+                const float *invd, float *z, double *part, const PcgScalars *sc) {
   hipLaunchKernelGGL(k_f32_pass_b, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, e, p,
-                     r, y, invd, part, (long long)c->red_cap, sc);
+                     r, y, invd, z, part, (long long)c->red_cap, sc);
 }
 
 void f32_add_to(const sts_ctx *c, double *x, const float *e) {

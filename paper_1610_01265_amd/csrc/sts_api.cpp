@@ -748,10 +748,10 @@ static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, d
   sts_status st = pcg_workspace(ctx, STS_PC_JACOBI, one, &fac);
   if (st) return st;
   const long long n = ctx->ncell, cap = ctx->red_cap;
-  if ((st = dalloc(ctx, (void **)&ctx->d_pcg32, (size_t)6 * n * 4))) return st;
+  if ((st = dalloc(ctx, (void **)&ctx->d_pcg32, (size_t)7 * n * 4))) return st;
   double *b = ctx->d_pcg, *invd = b + n, *r64 = b + 2 * n;
   float *iv = ctx->d_pcg32, *e = iv + n, *r = iv + 2 * n, *p0 = iv + 3 * n, *p1 = iv + 4 * n,
-        *y = iv + 5 * n;
+        *y = iv + 5 * n, *z = iv + 6 * n;
   double *part = ctx->d_red;
   PcgScalars *sc = ctx->d_sc, *h = (PcgScalars *)ctx->h_pin;
   launch_be_rhs(ctx, u_n, dt, b, invd, part + 2 * cap);
@@ -769,7 +769,7 @@ static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, d
     rel = hh[1] > 0 ? std::sqrt(hh[0] / hh[1]) : 0.0;
     if (!std::isfinite(rel)) FAIL(STS_BREAKDOWN, "FP32 form: non-finite residual");
     if (rel <= rtol || total >= maxit) break;
-    f32_inner_init(ctx, r64, invd, r, iv, e, part);
+    f32_inner_init(ctx, r64, invd, r, iv, e, z, part);
     launch_finalize_init_n(ctx, part + cap, np1, part + cap, np1, part, np1, sc, kInnerTol,
                            maxit - total);
     LAUNCHCHK();
@@ -777,9 +777,9 @@ static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, d
     HIPCHK(hipStreamSynchronize(ctx->stream));
     float *pold = p0, *pnew = p1;
     for (int it = 0; it < maxit - total && !h->done; ++it) {
-      f32_pass_a(ctx, dt, r, iv, pold, pnew, y, part, sc, it == 0);
+      f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
       launch_finalize_alpha(ctx, part, np3, sc);
-      f32_pass_b(ctx, e, pnew, r, y, iv, part, sc);
+      f32_pass_b(ctx, e, pnew, r, y, iv, z, part, sc);
       launch_finalize_beta(ctx, part, np1, sc);
       LAUNCHCHK();
       std::swap(pold, pnew);
@@ -847,7 +847,9 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
     launch_ilu_apply_init(ctx, blk, fac, r, z);
     LAUNCHCHK();
   }
-  launch_init_p(ctx, r, invd, ilu ? z : nullptr, p0, part + 2 * cap);
+  // both preconditioners keep z in its own array: pass A forms p = z + beta p
+  // from two streamed arrays
+  launch_init_p(ctx, r, invd, ilu ? z : nullptr, p0, part + 2 * cap, ilu ? nullptr : z);
   LAUNCHCHK();
   launch_finalize_init3(ctx, part + cap, part, part + 2 * cap, sc, rtol, maxit);
   LAUNCHCHK();
@@ -858,12 +860,12 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int it = 0; it < maxit && !h->done; ++it) {
-    launch_pass_a(ctx, dt, r, invd, ilu ? z : nullptr, pold, pnew, y, part, sc, it == 0);
+    launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
     launch_finalize_alpha(ctx, part, stencil_parts(ctx), sc);
     if (ilu)
       launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
     else
-      launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, part, sc);
+      launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, z, part, sc);
     launch_finalize_beta(ctx, part, nb_parts, sc);
     LAUNCHCHK();
     std::swap(pold, pnew);
@@ -908,6 +910,8 @@ sts_status sts_be_residual(sts_ctx *ctx, const double *u_n, const double *x, dou
 // ---------------------------------------------------------------------------
 // Resistive diffusion of the vector potential on cell edges (Eq. mhd:a).
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
 namespace {
 
 // centres, centre gaps across each face position, and the centres before /
@@ -942,6 +946,8 @@ AxisGeo axis_geo(const std::vector<double> &f, bool per) {
 }
 
 }  // namespace
+
+extern "C" {
 
 sts_status sts_set_resistivity(sts_ctx *ctx, double eta) {
   if (!ctx) return STS_EINVAL;

@@ -95,7 +95,7 @@ struct sts_ctx {
   int rk_ncomp = 0;
   float *d_rk32 = nullptr;    // FP32 form RKL2: F0, delta_a, delta_b
   int rk32_ncomp = 0;
-  float *d_pcg32 = nullptr;   // FP32 form PCG: 1/A_ii, e, r, p0, p1, y
+  float *d_pcg32 = nullptr;   // FP32 form PCG: 1/A_ii, e, r, p0, p1, y, z
   double *d_pcg = nullptr;    // PCG vectors
   double *d_red = nullptr;    // reduction partials
   int red_cap = 0;
@@ -178,14 +178,14 @@ void f32_apply(const sts_ctx *c, int ncomp, const double *u, double *Fu);
 void f32_stage(const sts_ctx *c, int last, int ncomp, const float *dkm1, const float *dkm2,
                const float *F0, void *out, const double *u0, double mu, double nu, double mut_dt,
                double g_dt);
-void f32_pass_a(const sts_ctx *c, double dt, const float *r, const float *invd, const float *pold,
-                float *pnew, float *y, double *part, const PcgScalars *sc, int first);
+void f32_pass_a(const sts_ctx *c, double dt, const float *z, const float *pold, float *pnew,
+                float *y, double *part, const PcgScalars *sc, int first);
 void f32_residual(const sts_ctx *c, const double *b, const double *x, double dt, double *r,
                   double *part);
 void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, float *r,
-                    float *invd, float *e, double *part);
+                    float *invd, float *e, float *z, double *part);
 void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const float *y,
-                const float *invd, double *part, const PcgScalars *sc);
+                const float *invd, float *z, double *part, const PcgScalars *sc);
 void f32_add_to(const sts_ctx *c, double *x, const float *e);
 void launch_fill_f32(const sts_ctx *c, float *p, long long n, float v);
 
@@ -198,19 +198,21 @@ void launch_be_rhs(const sts_ctx *c, const double *u_n, double dt, double *b, do
 void launch_residual_init(const sts_ctx *c, const double *b, const double *x, double dt,
                           const double *invd, const double *zilu, double *r, double *p,
                           double *part);
+// zout (may be null): where the Jacobi z = r / A_ii is stored for pass A
 void launch_init_p(const sts_ctx *c, const double *r, const double *invd, const double *zilu,
-                   double *p, double *part);
+                   double *p, double *part, double *zout);
 void launch_finalize_init_n(const sts_ctx *c, const double *pb, int nb, const double *prr,
                             int nrr, const double *prz, int nrz, PcgScalars *sc, double rtol,
                             int maxit);
 void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr,
                            const double *prz, PcgScalars *sc, double rtol, int maxit);
-void launch_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
-                   const double *zilu, const double *pold, double *pnew, double *y, double *part,
-                   const PcgScalars *sc, int first);
+// pass A: p = z + beta p_old (z stored by the previous pass), y = A p, partial p.y
+void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *pold,
+                   double *pnew, double *y, double *part, const PcgScalars *sc, int first);
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
+// also stores z = r / A_ii of the updated residual for the next pass A
 void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
-                          const double *y, const double *invd, double *part,
+                          const double *y, const double *invd, double *z, double *part,
                           const PcgScalars *sc);
 void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
 void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,

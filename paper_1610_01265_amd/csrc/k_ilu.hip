@@ -117,9 +117,12 @@ __global__ void __launch_bounds__(FTH)
     }
   }
   __syncthreads();
+  // Phase 2 runs on wavefront 0 alone: its LDS operations complete in order,
+  // so a wave-level compiler barrier separates the levels.
   const int li = t >> 3, lj = t & 7;
-  const bool col = t < 64 && li < e0 && lj < e1;
+  const bool col = li < e0 && lj < e1;
   const int nlev = 3 * (e0 - 1) + 2 * (e1 - 1) + (e2 - 1) + 1;
+  if (t < 64)
   for (int lev = 0; lev < nlev; ++lev) {
     const int lk = lev - 3 * li - 2 * lj;
     if (col && lk >= 0 && lk < e2) {
@@ -150,8 +153,9 @@ __global__ void __launch_bounds__(FTH)
       sD[l] = dii;
       if (!(dii > 0.0)) atomicOr(bad, 1);
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
+  __syncthreads();
   double *fb = fac + (size_t)bid * 10 * BS;
   for (int l = t; l < BS; l += FTH) {
 #pragma unroll
@@ -304,10 +308,22 @@ __global__ void __launch_bounds__(ATH)
 constexpr int B8 = 8, BS8 = 512;
 constexpr int PADZ = (B8 + 1) * B8 + 1;  // largest |offset| of a lower neighbour
 constexpr int LROW = BS8 + PADZ;
+// Persistent form: workgroup w takes blocks w, w + G, w + 2G, ... (G =
+// gridDim.x, at most the number of workgroups resident at once).  While one
+// wavefront runs a block's two substitution sweeps out of LDS, every
+// wavefront's loads of the next block's factors and vectors are in flight
+// into registers, so HBM latency overlaps the latency-bound sweeps.
+struct Blk8 {
+  double f[10][BS8 / ATH];  // L (9 slots) and 1/D of this thread's cells
+  double xv[BS8 / ATH], pv[BS8 / ATH], rv[BS8 / ATH], yv[BS8 / ATH];
+  int c[BS8 / ATH];         // grid index (clamped into the grid)
+  bool v[BS8 / ATH];        // cell inside the grid
+};
+
 template <bool UPDATE>
 __global__ void __launch_bounds__(ATH)
-    k_ilu_apply8(Grid g, BlockGeo bg, const double *__restrict__ fac, double *__restrict__ x,
-                 const double *__restrict__ p, double *__restrict__ r,
+    k_ilu_apply8(Grid g, BlockGeo bg, int nblk, const double *__restrict__ fac,
+                 double *__restrict__ x, const double *__restrict__ p, double *__restrict__ r,
                  const double *__restrict__ y, double *__restrict__ z, double *part,
                  long long cap, const PcgScalars *sc) {
   if (UPDATE && sc->done) return;
@@ -315,117 +331,142 @@ __global__ void __launch_bounds__(ATH)
   __shared__ double sI[BS8];
   __shared__ double szp[PADZ + BS8 + PADZ];
   double *sz = szp + PADZ;
-  const int bid = blockIdx.x, t = threadIdx.x;
-  int o0, o1, o2, e0, e1, e2;
-  bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
-  const double *fb = fac + (size_t)bid * 10 * BS8;
+  const int t = threadIdx.x;
   const double alpha = UPDATE ? sc->alpha : 0.0;
   constexpr int PER = BS8 / ATH;
-  // factors -> LDS, pads -> 0
-#pragma unroll
-  for (int s = 0; s < 10; ++s) {
-    double v[PER];
-#pragma unroll
-    for (int m = 0; m < PER; ++m) v[m] = fb[s * BS8 + t + ATH * m];
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      if (s < 9)
-        sL[s * LROW + t + ATH * m] = v[m];
-      else
-        sI[t + ATH * m] = v[m];
-    }
-  }
+  // pads -> 0 (the per-block staging below never writes them)
   for (int q = t; q < 9 * PADZ; q += ATH) sL[(q / PADZ) * LROW + BS8 + q % PADZ] = 0.0;
   for (int q = t; q < PADZ; q += ATH) {
     szp[q] = 0.0;
     szp[PADZ + BS8 + q] = 0.0;
   }
-  // x, r updates; r -> LDS (missing cells of edge blocks: 0)
-  int cidx[PER];
-  bool cval[PER];
+  auto fetch = [&](int bid, Blk8 &B) {
+    int o0, o1, o2, e0, e1, e2;
+    bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
+    const double *fb = fac + (size_t)bid * 10 * BS8;
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int l = t + ATH * m;
-    const int li = l >> 6, lj = (l >> 3) & 7, lk = l & 7;
-    cval[m] = li < e0 && lj < e1 && lk < e2;
-    cidx[m] = lin(g, o0 + min(li, e0 - 1), o1 + min(lj, e1 - 1), o2 + min(lk, e2 - 1));
-  }
-  double rl[PER];
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int c = cidx[m];
-    if (UPDATE) {
-      const double xv = x[c], pv = p[c], rv = r[c], yv = y[c];
-      rl[m] = cval[m] ? rv - alpha * yv : 0.0;
-      if (cval[m]) {
-        x[c] = xv + alpha * pv;
-        r[c] = rl[m];
-      }
-    } else {
-      const double rv = r[c];
-      rl[m] = cval[m] ? rv : 0.0;
+    for (int m = 0; m < PER; ++m) {
+      const int l = t + ATH * m;
+      const int li = l >> 6, lj = (l >> 3) & 7, lk = l & 7;
+      B.v[m] = li < e0 && lj < e1 && lk < e2;
+      B.c[m] = lin(g, o0 + min(li, e0 - 1), o1 + min(lj, e1 - 1), o2 + min(lk, e2 - 1));
     }
-    sz[t + ATH * m] = rl[m];
-  }
-  __syncthreads();
-  // lower-neighbour offsets (ascending lexicographic order, as c_off)
+#pragma unroll
+    for (int s = 0; s < 10; ++s)
+#pragma unroll
+      for (int m = 0; m < PER; ++m) B.f[s][m] = fb[s * BS8 + t + ATH * m];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      B.rv[m] = r[B.c[m]];
+      if (UPDATE) {
+        B.xv[m] = x[B.c[m]];
+        B.pv[m] = p[B.c[m]];
+        B.yv[m] = y[B.c[m]];
+      }
+    }
+  };
   constexpr int LO[9] = {-72, -65, -64, -63, -56, -9, -8, -7, -1};
-  if (t < 64) {
-    const int li = t >> 3, lj = t & 7;
-    const int d = 3 * li + 2 * lj;
-    constexpr int NLEV = 3 * 7 + 2 * 7 + 7 + 1;
-    auto sum9 = [](const double *lv, const double *zv) {
-      const double a = lv[0] * zv[0] + lv[1] * zv[1], b = lv[2] * zv[2] + lv[3] * zv[3];
-      const double c = lv[4] * zv[4] + lv[5] * zv[5], e = lv[6] * zv[6] + lv[7] * zv[7];
-      return ((a + b) + (c + e)) + lv[8] * zv[8];
-    };
-    // forward: z*_i = r_i - sum_k L_ik z*_k
-    for (int lev = 0; lev < NLEV; ++lev) {
-      const int lk = lev - d;
-      if (lk >= 0 && lk < B8) {
-        const int l = t * B8 + lk;
-        const double *zr = sz + l;
-        const double *lr = sL + l;
-        double lv[9], zv[9];
-#pragma unroll
-        for (int s = 0; s < 9; ++s) {
-          lv[s] = lr[s * LROW];
-          zv[s] = zr[LO[s]];
-        }
-        sz[l] = zr[0] - sum9(lv, zv);
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
-    // backward: z_i = z*_i / D_i - sum_j L_ji z_j over upper neighbours j = i - LO[s]
-    for (int lev = NLEV - 1; lev >= 0; --lev) {
-      const int lk = lev - d;
-      if (lk >= 0 && lk < B8) {
-        const int l = t * B8 + lk;
-        const double *zr = sz + l;
-        double lv[9], zv[9];
-#pragma unroll
-        for (int s = 0; s < 9; ++s) {
-          lv[s] = sL[s * LROW + l - LO[s]];
-          zv[s] = zr[-LO[s]];
-        }
-        sz[l] = zr[0] * sI[l] - sum9(lv, zv);
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  __syncthreads();
+  auto sum9 = [](const double *lv, const double *zv) {
+    const double a = lv[0] * zv[0] + lv[1] * zv[1], b = lv[2] * zv[2] + lv[3] * zv[3];
+    const double c = lv[4] * zv[4] + lv[5] * zv[5], e = lv[6] * zv[6] + lv[7] * zv[7];
+    return ((a + b) + (c + e)) + lv[8] * zv[8];
+  };
   double rz = 0.0, rr = 0.0;
+  Blk8 B;
+  int bid = blockIdx.x;
+  if (bid < nblk) fetch(bid, B);
+  for (; bid < nblk; bid += gridDim.x) {
+    // stage this block: factors -> LDS; x, r updates; r -> LDS (0 outside the grid)
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int l = t + ATH * m;
-    if (cval[m]) {
-      const double zv = sz[l];
-      z[cidx[m]] = zv;
-      rz += rl[m] * zv;
-      rr += rl[m] * rl[m];
+    for (int s = 0; s < 10; ++s)
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        if (s < 9)
+          sL[s * LROW + t + ATH * m] = B.f[s][m];
+        else
+          sI[t + ATH * m] = B.f[s][m];
+      }
+    double rl[PER], xn[PER];
+    int cidx[PER];
+    bool cval[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      cidx[m] = B.c[m];
+      cval[m] = B.v[m];
+      if (UPDATE) {
+        rl[m] = cval[m] ? B.rv[m] - alpha * B.yv[m] : 0.0;
+        xn[m] = B.xv[m] + alpha * B.pv[m];
+      } else {
+        rl[m] = cval[m] ? B.rv[m] : 0.0;
+      }
+      sz[t + ATH * m] = rl[m];
     }
+    // stores after every prefetched operand is consumed: vector memory
+    // counters complete in order, so a store issued earlier would make the
+    // wait for a later load also wait for the store
+    if (UPDATE) {
+#pragma unroll
+      for (int m = 0; m < PER; ++m)
+        if (cval[m]) {
+          x[cidx[m]] = xn[m];
+          r[cidx[m]] = rl[m];
+        }
+    }
+    __syncthreads();
+    // the next block's loads go out before the sweeps
+    if (bid + (int)gridDim.x < nblk) fetch(bid + gridDim.x, B);
+    if (t < 64) {
+      const int li = t >> 3, lj = t & 7;
+      const int d = 3 * li + 2 * lj;
+      constexpr int NLEV = 3 * 7 + 2 * 7 + 7 + 1;
+      // forward: z*_i = r_i - sum_k L_ik z*_k
+      for (int lev = 0; lev < NLEV; ++lev) {
+        const int lk = lev - d;
+        if (lk >= 0 && lk < B8) {
+          const int l = t * B8 + lk;
+          const double *zr = sz + l;
+          const double *lr = sL + l;
+          double lv[9], zv[9];
+#pragma unroll
+          for (int s = 0; s < 9; ++s) {
+            lv[s] = lr[s * LROW];
+            zv[s] = zr[LO[s]];
+          }
+          sz[l] = zr[0] - sum9(lv, zv);
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      // backward: z_i = z*_i / D_i - sum_j L_ji z_j over upper neighbours j = i - LO[s]
+      for (int lev = NLEV - 1; lev >= 0; --lev) {
+        const int lk = lev - d;
+        if (lk >= 0 && lk < B8) {
+          const int l = t * B8 + lk;
+          const double *zr = sz + l;
+          double lv[9], zv[9];
+#pragma unroll
+          for (int s = 0; s < 9; ++s) {
+            lv[s] = sL[s * LROW + l - LO[s]];
+            zv[s] = zr[-LO[s]];
+          }
+          sz[l] = zr[0] * sI[l] - sum9(lv, zv);
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int l = t + ATH * m;
+      if (cval[m]) {
+        const double zv = sz[l];
+        z[cidx[m]] = zv;
+        rz += rl[m] * zv;
+        rr += rl[m] * rl[m];
+      }
+    }
+    __syncthreads();  // the LDS is restaged for the next block
   }
-  if (part) wg_sum2<ATH>(rz, rr, t, part + bid, part + cap + bid);
+  if (part) wg_sum2<ATH>(rz, rr, t, part + blockIdx.x, part + cap + blockIdx.x);
 }
 
 BlockGeo block_geo(const sts_ctx *c, const int block[3]) {
@@ -445,7 +486,20 @@ int ilu_nblocks(const sts_ctx *c, const int block[3]) {
          ((c->n2 + block[2] - 1) / block[2]);
 }
 
-int ilu_parts(const sts_ctx *c, const int block[3]) { return ilu_nblocks(c, block); }
+// Workgroups of the persistent 8^3 apply: at most three per CU are resident
+// (51.5 KB of LDS each) on the 256 CUs; the blocks are spread evenly.
+static int ilu8_grid(int nb) {
+  constexpr int kResident = 3 * 256;
+  const int per = (nb + kResident - 1) / kResident;
+  return (nb + per - 1) / per;
+}
+
+bool is8(const int block[3]) { return block[0] == 8 && block[1] == 8 && block[2] == 8; }
+
+int ilu_parts(const sts_ctx *c, const int block[3]) {
+  const int nb = ilu_nblocks(c, block);
+  return is8(block) ? ilu8_grid(nb) : nb;
+}
 
 void launch_ilu_factor(const sts_ctx *c, double dt, const int block[3], double *fac, int *bad) {
   const int nb = ilu_nblocks(c, block);
@@ -457,14 +511,13 @@ void launch_ilu_factor(const sts_ctx *c, double dt, const int block[3], double *
                        c->coef(), dt, block_geo(c, block), fac, bad);
 }
 
-bool is8(const int block[3]) { return block[0] == 8 && block[1] == 8 && block[2] == 8; }
-
 void launch_ilu_apply_init(const sts_ctx *c, const int block[3], const double *fac,
                            const double *r, double *z) {
   const int nb = ilu_nblocks(c, block);
   if (is8(block)) {
-    hipLaunchKernelGGL(k_ilu_apply8<false>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
-                       block_geo(c, block), fac, (double *)nullptr, (const double *)nullptr,
+    hipLaunchKernelGGL(k_ilu_apply8<false>, dim3(ilu8_grid(nb)), dim3(ATH), 0, c->stream,
+                       c->grid(), block_geo(c, block), nb, fac, (double *)nullptr,
+                       (const double *)nullptr,
                        const_cast<double *>(r), (const double *)nullptr, z, (double *)nullptr,
                        0LL, (const PcgScalars *)nullptr);
     return;
@@ -480,8 +533,9 @@ void launch_pass_b_ilu(const sts_ctx *c, const int block[3], const double *fac, 
                        const PcgScalars *sc) {
   const int nb = ilu_nblocks(c, block);
   if (is8(block)) {
-    hipLaunchKernelGGL(k_ilu_apply8<true>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),
-                       block_geo(c, block), fac, x, p, r, y, z, part, (long long)c->red_cap, sc);
+    hipLaunchKernelGGL(k_ilu_apply8<true>, dim3(ilu8_grid(nb)), dim3(ATH), 0, c->stream,
+                       c->grid(), block_geo(c, block), nb, fac, x, p, r, y, z, part,
+                       (long long)c->red_cap, sc);
     return;
   }
   hipLaunchKernelGGL(k_ilu_apply<true>, dim3(nb), dim3(ATH), 0, c->stream, c->grid(),

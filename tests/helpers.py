@@ -75,4 +75,35 @@ def window_F(w, cells, half=2):
     return np.array(out)
 
 
-__all__ = ["oracle_spitzer", "gpu_spitzer", "small_shell", "relmax", "window_F", "make_workload"]
+def window_op(w, cell, half, kind="spitzer", nu=1.0):
+    """The oracle operator on the window of half-width `half` around `cell`
+    (clipped at the r and theta walls, phi unwrapped), with the real boundary
+    conditions where the window reaches the domain's boundary.  Returns
+    (op, take, centre): take() cuts a full-grid field to the window; centre
+    is the cell's index in it.  Rows of cells within `half` - 2 of the centre
+    are exact rows of the full operator."""
+    rf, thf, phf = w["rf"], w["thf"], w["phf"]
+    n0, n1, n2 = len(rf) - 1, len(thf) - 1, len(phf) - 1
+    i, j, k = cell
+    i0, i1 = max(0, i - half), min(n0, i + half + 1)
+    j0, j1 = max(0, j - half), min(n1, j + half + 1)
+    ks = [(k + d) % n2 for d in range(-half, half + 1)]
+    pf = [phf[ks[0]]]
+    for kk in ks:
+        pf.append(pf[-1] + (phf[kk + 1] - phf[kk]))
+    pf = np.array(pf)
+    sl = (slice(i0, i1), slice(j0, j1))
+    take = lambda a: np.ascontiguousarray(a[sl][:, :, ks])  # noqa: E731
+    bc = (O.DIRICHLET if i0 == 0 else O.ZEROFLUX,) + (O.ZEROFLUX,) * 5
+    if kind == "spitzer":
+        D = O.spitzer_tensor(take(w["T"]), w["kappa0"], take(w["br"]), take(w["bt"]),
+                             take(w["bp"]))
+        u_lo = w["T_inner"]
+    else:
+        D = O.isotropic_tensor((i1 - i0, j1 - j0, len(ks)), nu)
+        u_lo = 0.0
+    op = O.assemble("spherical", rf[i0:i1 + 1], thf[j0:j1 + 1], pf, D, bc, u_lo=u_lo)
+    return op, take, (i - i0, j - j0, half)
+
+
+__all__ = ["oracle_spitzer", "window_op", "gpu_spitzer", "small_shell", "relmax", "window_F", "make_workload"]

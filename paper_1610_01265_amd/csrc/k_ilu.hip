@@ -62,6 +62,14 @@ constexpr PairTab make_pairs() {
 
 __constant__ PairTab c_pairs = make_pairs();
 
+// XCD-aware order: workgroup w runs on XCD w % 8.  The returned logical
+// index gives each XCD a contiguous range, so neighbouring blocks (which
+// share cache lines of the grid-layout arrays along phi) meet in one L2.
+__device__ __forceinline__ int xcd_order(int w, int nwg) {
+  const int q8 = nwg >> 3, r8 = nwg & 7, x8 = w & 7, s8 = w >> 3;
+  return x8 < r8 ? x8 * (q8 + 1) + s8 : r8 * (q8 + 1) + (x8 - r8) * q8 + s8;
+}
+
 struct BlockGeo {
   int B0, B1, B2, nbj, nbk;
   __device__ __forceinline__ void origin(const Grid &g, int bid, int &o0, int &o1, int &o2,
@@ -94,7 +102,7 @@ __global__ void __launch_bounds__(FTH)
     k_ilu_factor(Grid g, Coef C, double dt, BlockGeo bg, double *__restrict__ fac, int *bad) {
   __shared__ double sL[9][MAXB];
   __shared__ double sD[MAXB];
-  const int bid = blockIdx.x, t = threadIdx.x;
+  const int bid = xcd_order(blockIdx.x, gridDim.x), t = threadIdx.x;
   int o0, o1, o2, e0, e1, e2;
   bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
   const int B1 = bg.B1, B2 = bg.B2, BS = bg.B0 * B1 * B2;
@@ -181,7 +189,7 @@ __global__ void __launch_bounds__(ATH)
   __shared__ double sI[MAXB];  // 1 / D
   __shared__ double sz[MAXB];
   __shared__ double sr[MAXB];
-  const int bid = blockIdx.x, t = threadIdx.x;
+  const int bid = xcd_order(blockIdx.x, gridDim.x), t = threadIdx.x;
   int o0, o1, o2, e0, e1, e2;
   bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
   const int B1 = bg.B1, B2 = bg.B2, BS = bg.B0 * B1 * B2;

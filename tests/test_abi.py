@@ -55,6 +55,46 @@ def test_create_rejects_bad_arguments_without_gpu_work(lib):
     assert st == -1 and not h.value
 
 
+BAD_CREATE = [
+    # (coord, n, bc, face arrays: "ok" | "dec" | "neg" | "pole"), each rejected on the host
+    (0, (2048, 2048, 1024), (0, 0, 0, 0, 2, 2), "ok"),   # 4.3e9 cells: 32-bit indices overflow
+    (0, (0, 4, 4), (0, 0, 0, 0, 2, 2), "ok"),            # empty axis
+    (0, (4, 4, 4), (0, 0, 0, 0, 2, 0), "ok"),            # periodic on one side only
+    (0, (4, 4, 2), (0, 0, 0, 0, 2, 2), "ok"),            # periodic axis with < 3 cells
+    (0, (4, 4, 4), (0, 0, 1, 0, 2, 2), "ok"),            # Dirichlet off axis 0
+    (0, (4, 4, 4), (0, 0, 0, 0, 2, 7), "ok"),            # unknown boundary condition
+    (5, (4, 4, 4), (0, 0, 0, 0, 2, 2), "ok"),            # unknown coordinate system
+    (0, (4, 4, 4), (0, 0, 0, 0, 2, 2), "dec"),           # faces not increasing
+    (0, (4, 4, 4), (0, 0, 0, 0, 2, 2), "neg"),           # non-positive radius
+    (0, (4, 4, 4), (0, 0, 0, 0, 2, 2), "pole"),          # colatitude reaches pi
+]
+
+
+@pytest.mark.parametrize("coord,n,bc,faces", BAD_CREATE)
+def test_create_rejects_each_bad_argument(lib, coord, n, bc, faces):
+    """Each invalid grid, boundary set or coordinate array is STS_EINVAL with
+    no handle, decided on the host (no GPU is needed to run this test)."""
+    import math
+    import numpy as np
+    lib.sts_create.restype = ctypes.c_int
+    m = max(n) + 1
+    r = np.linspace(1.0, 2.0, m)
+    th = np.linspace(0.1, 0.9 * math.pi, m)
+    ph = np.linspace(0.0, 2 * math.pi, m)
+    if faces == "dec":
+        th = th[::-1].copy()
+    elif faces == "neg":
+        r = np.linspace(-1.0, 2.0, m)
+    elif faces == "pole":
+        th = np.linspace(0.1, math.pi, m)
+    arrs = [np.ascontiguousarray(a) for a in (r, th, ph)]
+    ptr = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs]
+    h = ctypes.c_void_p()
+    cbc = (ctypes.c_int * 6)(*bc)
+    st = lib.sts_create(ctypes.byref(h), coord, n[0], n[1], n[2], *ptr, cbc, None)
+    assert st == -1 and not h.value
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_1610_01265_amd import _binding
     monkeypatch.setattr(_binding, "LIB_PATH", str(tmp_path / "nope.so"))

@@ -39,29 +39,39 @@ __device__ __forceinline__ void wg_sum2(double a, double b, int tid, double *out
 }
 
 // Sum part[0..n) (and part[stride..stride+n) when two) with one workgroup of
-// 256 threads, in a fixed order.
+// 256 threads, in a fixed order: each thread issues its (up to) 8 loads of a
+// 2048-entry round at once, then wave shuffles and the four wave totals in
+// a fixed order.  (One round of independent loads instead of a chain of
+// dependent ones; the finalizers sit between every two PCG sweeps.)
 __device__ __forceinline__ void block_sum_parts(const double *part, int n, long long stride,
                                                 double *s0, double *s1) {
   const int tid = threadIdx.x;
   double a = 0.0, b = 0.0;
-  for (int t = tid; t < n; t += 256) {
-    a += part[t];
-    if (s1) b += part[stride + t];
-  }
-  __shared__ double ra[256], rb[256];
-  ra[tid] = a;
-  rb[tid] = b;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) {
-      ra[tid] += ra[tid + h];
-      rb[tid] += rb[tid + h];
+  for (int t0 = 0; t0 < n; t0 += 8 * 256) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int t = t0 + tid + 256 * q;
+      va[q] = t < n ? part[t] : 0.0;
+      vb[q] = (s1 && t < n) ? part[stride + t] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      a += va[q];
+      b += vb[q];
+    }
   }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __shared__ double ra[4], rb[4];
+  if ((tid & 63) == 0) {
+    ra[tid >> 6] = a;
+    rb[tid >> 6] = b;
+  }
+  __syncthreads();
   if (tid == 0) {
-    *s0 = ra[0];
-    if (s1) *s1 = rb[0];
+    *s0 = (ra[0] + ra[1]) + (ra[2] + ra[3]);
+    if (s1) *s1 = (rb[0] + rb[1]) + (rb[2] + rb[3]);
   }
 }
 

@@ -65,9 +65,9 @@ def parse():
     ap.add_argument("--march-steps", type=int, default=10,
                     help="successive steps per method in the march run after the timed steps "
                          "(0 skips it)")
-    ap.add_argument("--learned-train-seeds", type=int, default=24,
+    ap.add_argument("--learned-train-seeds", type=int, default=200,
                     help="training pairs (seeds 1..N) for the network before the timed steps")
-    ap.add_argument("--learned-epochs", type=int, default=3)
+    ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--copy-calib", action="store_true",
                     help="before the steps, run a plain device copy of 4 fields (known bytes) "
                          "that calibrates the HBM byte counters")

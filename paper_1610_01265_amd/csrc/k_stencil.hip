@@ -33,20 +33,11 @@ namespace {
 #ifndef STS_MARCH_WG
 #define STS_MARCH_WG 1024  // about one round of 4 workgroups per CU
 #endif
-// STS_PF: per-cell operands loaded one plane ahead (1), only the cell's own
-// streams one plane ahead (2), or all at their plane (0).
-// STS_HALO: the stencil-input plane staged into LDS at the end of iteration i
-// is loaded during iteration i before (1) or after (3) this plane's per-cell
-// loads, or during iteration i - 1 (2).  Vector loads complete in order, so in
-// (1) and (2) the row's wait for its per-cell operands also waits for the
-// prefetch; (3) issues the prefetch last and unconditionally (same loads on
-// every lane and iteration), so it stays in flight across the row.
-#ifndef STS_PF
-#define STS_PF 0
-#endif
-#ifndef STS_HALO
-#define STS_HALO 3
-#endif
+// The stencil-input plane staged into LDS at the end of iteration i is
+// loaded after that plane's per-cell operands and on every lane and
+// iteration: vector loads complete in order, so the row's wait for its
+// operands does not wait for the prefetch, which stays in flight across the
+// row.
 constexpr int TK = 64, TJ = STS_MARCH_TJ, NT = TK * TJ;
 constexpr int HK = TK + 2, HJ = TJ + 2, PL = HK * HJ;  // one LDS plane (tile + halo)
 constexpr int NLOAD = (PL + NT - 1) / NT;
@@ -259,30 +250,14 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     pk01B = R(C.k01[cA + tg.dJm]);
     pk02C = R(C.k02[cA + tg.dKm]);
   }
-  Loads cur, nxt;
-  if (STS_PF == 1) load_plane_cells(i0, cur);
-  if (STS_PF == 2) load_own(i0, cur);
-  R vn[NLOAD];  // STS_HALO == 2: plane i + 3 in flight
-  if (STS_HALO == 2 && i0 + 2 <= i1) load_plane(i0 + 2, v);
+  Loads cur;
   double acc_a = 0.0, acc_b = 0.0;
   __syncthreads();
 
   for (int i = i0; i < i1; ++i) {
     const bool pre = i + 2 <= i1;
-    if (STS_HALO == 1) {
-      if (pre) load_plane(i + 2, v);
-    } else if (STS_HALO == 2) {
-      if (i + 3 <= i1) load_plane(i + 3, vn);
-    }
-    if (STS_PF == 1) {
-      if (i + 1 < i1) load_plane_cells(i + 1, nxt);
-    } else if (STS_PF == 2) {
-      load_nbr(i, cur);
-      if (i + 1 < i1) load_own(i + 1, nxt);
-    } else {
-      load_plane_cells(i, cur);
-    }
-    if (STS_HALO == 3) load_plane(i + 2, v);
+    load_plane_cells(i, cur);
+    load_plane(i + 2, v);  // clamped / wrapped plane index: always in the grid
     if (active) {
       PlaneGeo<R> pg;
       pg.A = nbr(i, g.n0, g.per0);
@@ -383,275 +358,13 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
       pk01B = cur.k01B;
       pk02C = cur.k02C;
     }
-    if (STS_PF) cur = nxt;  // (neighbour values of cur are reloaded at their plane)
     if (pre) store_plane(i + 2, v);
-    if (STS_HALO == 2) {
-#pragma unroll
-      for (int q = 0; q < NLOAD; ++q) v[q] = vn[q];
-    }
     __syncthreads();
   }
   if (MODE == M_PA || MODE == M_RES || MODE == M_RESN)
     wg_sum2<NT>(acc_a, acc_b, tid, a.part + w, a.part + a.cap + w);
 }
 
-// ---------------------------------------------------------------------------
-// Two RKL2 stages per sweep (temporal blocking of the recurrence of Fig.
-// "rkl2").  A workgroup owns a TJ2 x TK2 output tile and marches r-planes.
-// Stage k is evaluated on the tile extended by one cell in theta and phi (one
-// thread per extended cell) and kept in an LDS ring; stage k + 1 is evaluated
-// one plane behind on the tile from that ring:
-//   u_k     = mu_k u_{k-1} + nu_k u_{k-2} + (1 - mu_k - nu_k) u_0
-//             + mu~_k dt F(u_{k-1}) + gamma~_k dt F(u_0)
-//   u_{k+1} = mu_{k+1} u_k + nu_{k+1} u_{k-1} + ... + mu~_{k+1} dt F(u_k) + ...
-// A pair of stages reads u_{k-1}, u_{k-2}, u_0, F0 and the coefficients once
-// and writes u_k and u_{k+1}.  Stage k reads u_{k-2}, u_0 and F0 also on the
-// ring of cells owned by neighbouring workgroups, so neither output may
-// alias an input.  (Build option STS_RK_FUSE: on this tile shape the extended
-// region and the chunk-edge planes cost more stencil work than the saved
-// traffic; the single-stage march is the default.)  Planes outside [0, n0)
-// of a non-periodic axis 0 (and
-// cells outside the grid along axes 1, 2) are evaluated at the clamped index:
-// they only enter masked terms.
-constexpr int TK2 = 62, TJ2 = 4;            // output tile
-constexpr int EK = TK2 + 2, EJ = TJ2 + 2;   // extended region, one thread per cell
-constexpr int RK2_NT = EK * EJ;                // 384 threads
-constexpr int AK = EK + 2, AJ = EJ + 2;     // window of u_{k-1}: 66 x 8
-constexpr int PA2 = AK * AJ;
-constexpr int NLA = (PA2 + RK2_NT - 1) / RK2_NT;
-
-struct Args2 {
-  double *out1, *out2;          // u_k, u_{k+1}
-  const double *ukm2, *u0, *F0;
-  double mu1, nu1, mt1, gt1;    // stage k: mu, nu, mu~ dt, gamma~ dt
-  double mu2, nu2, mt2, gt2;    // stage k + 1
-};
-
-template <int OP>
-__global__ void __launch_bounds__(RK2_NT, 3)
-    k_rk2(Grid g, CoefS<double> C, const double *__restrict__ ukm1, Args2 a, int CI, int nchunk,
-          long long ncell) {
-  using R = double;
-  __shared__ R s_a[4][PA2];  // u_{k-1}: planes i-1 .. i+1 (+ one being staged)
-  __shared__ R s_b[4][RK2_NT];  // u_k on the extended region: planes i-2 .. i
-  const int tid = threadIdx.x;
-  const int el = tid % EK, ew = tid / EK;
-  const int nwg = gridDim.x, w = blockIdx.x;
-  const int q8 = nwg >> 3, r8 = nwg & 7, x8 = w & 7, s8 = w >> 3;
-  const int L = x8 < r8 ? x8 * (q8 + 1) + s8 : r8 * (q8 + 1) + (x8 - r8) * q8 + s8;
-  const int ntk = (g.n2 + TK2 - 1) / TK2, ntj = (g.n1 + TJ2 - 1) / TJ2;
-  const int bx = L % ntk, by = (L / ntk) % ntj, bz = L / (ntk * ntj);
-  const int k0 = bx * TK2, j0 = by * TJ2;
-  const int comp = bz / nchunk, chunk = bz - comp * nchunk;
-  const int i0 = chunk * CI, i1 = min(i0 + CI, g.n0);
-  const long long off = (long long)comp * ncell;
-  const long long n12 = (long long)g.n1 * g.n2;
-
-  int hoff[NLA];
-#pragma unroll
-  for (int q = 0; q < NLA; ++q) {
-    const int e = min(tid + q * RK2_NT, PA2 - 1);
-    const int hj = e / AK, hk = e - hj * AK;
-    hoff[q] = wrapclamp(j0 - 2 + hj, g.n1, g.per1) * g.n2 + wrapclamp(k0 - 2 + hk, g.n2, g.per2);
-  }
-  auto load_a = [&](int ip, R *v) {
-    const long long base = off + (long long)wrapclamp(ip, g.n0, g.per0) * n12;
-#pragma unroll
-    for (int q = 0; q < NLA; ++q) v[q] = ukm1[base + hoff[q]];
-  };
-  auto store_a = [&](int ip, const R *v) {
-    R *sp = s_a[ip & 3];
-#pragma unroll
-    for (int q = 0; q < NLA; ++q)
-      if (tid + q * RK2_NT < PA2) sp[tid + q * RK2_NT] = v[q];
-  };
-  R v[NLA];
-  for (int ip = i0 - 2; ip <= i0; ++ip) {
-    load_a(ip, v);
-    store_a(ip, v);
-  }
-
-  const int jj = j0 - 1 + ew, kk = k0 - 1 + el;  // this thread's (extended) cell
-  const int jc = wrapclamp(jj, g.n1, g.per1), kc = wrapclamp(kk, g.n2, g.per2);
-  const bool outc = ew >= 1 && ew <= TJ2 && el >= 1 && el <= TK2 && jj < g.n1 && kk < g.n2;
-  ThreadGeo<R> tg;
-  tg.B = nbr(jc, g.n1, g.per1);
-  tg.C = nbr(kc, g.n2, g.per2);
-  tg.t11m = T1(g, T_IL11, tg.B.m);
-  tg.t11 = T1(g, T_IL11, jc);
-  tg.t21m = T1(g, T_IL21, tg.B.m);
-  tg.t21 = T1(g, T_IL21, jc);
-  tg.t21p = T1(g, T_IL21, tg.B.p);
-  tg.t22m = T2(g, T_IL22, tg.C.m);
-  tg.t22 = T2(g, T_IL22, kc);
-  tg.v12 = T1(g, T_V1, jc) * T2(g, T_V2, kc);
-  tg.dJm = (tg.B.m - jc) * g.n2;
-  tg.dKm = tg.C.m - kc;
-  if (OP == OP_ISOTROPIC) {
-    tg.a01 = T1(g, T_A01, jc);
-    tg.a02 = T2(g, T_A02, kc);
-    tg.a11 = T1(g, T_A11, jc);
-    tg.a11m = T1(g, T_A11, tg.B.m);
-    tg.a12 = T2(g, T_A12, kc);
-    tg.a21 = T1(g, T_A21, jc);
-    tg.a22 = T2(g, T_A22, kc);
-    tg.a22m = T2(g, T_A22, tg.C.m);
-  }
-  auto plane_geo = [&](int ic) {
-    PlaneGeo<R> pg;
-    pg.A = nbr(ic, g.n0, g.per0);
-    pg.s00m = T0(g, T_IL00, pg.A.m);
-    pg.s00 = T0(g, T_IL00, ic);
-    pg.s10m = T0(g, T_IL10, pg.A.m);
-    pg.s10 = T0(g, T_IL10, ic);
-    pg.s10p = T0(g, T_IL10, pg.A.p);
-    pg.s20m = T0(g, T_IL20, pg.A.m);
-    pg.s20 = T0(g, T_IL20, ic);
-    pg.s20p = T0(g, T_IL20, pg.A.p);
-    pg.v0 = T0(g, T_V0, ic);
-    if (OP == OP_ISOTROPIC) {
-      pg.a00 = T0(g, T_A00, ic);
-      pg.a00m = T0(g, T_A00, pg.A.m);
-      pg.a10 = T0(g, T_A10, ic);
-      pg.a20 = T0(g, T_A20, ic);
-    }
-    return pg;
-  };
-  // the row coefficients of the cell at plane ic: this plane's (own and
-  // same-plane neighbours) and the previous plane's w0, k01, k02, k01B, k02C
-  struct Own {
-    R w0, w1, w2, k01, k02, k12, w1B, k01B, k12B, w2C, k02C, k12C, k12BC;
-  };
-  auto load_own = [&](int ic, Own &o) {
-    if (OP == OP_SPITZER) {
-      const int c = (ic * g.n1 + jc) * g.n2 + kc;
-      const int cB = c + tg.dJm, cC = c + tg.dKm;
-      o.w0 = C.w0[c];
-      o.w1 = C.w1[c];
-      o.w2 = C.w2[c];
-      o.k01 = C.k01[c];
-      o.k02 = C.k02[c];
-      o.k12 = C.k12[c];
-      o.w1B = C.w1[cB];
-      o.k01B = C.k01[cB];
-      o.k12B = C.k12[cB];
-      o.w2C = C.w2[cC];
-      o.k02C = C.k02[cC];
-      o.k12C = C.k12[cC];
-      o.k12BC = C.k12[cB + tg.dKm];
-    }
-  };
-  auto row_coef = [&](const Own &o, R pw0, R pk01, R pk02, R pk01B, R pk02C) {
-    RowCoef<R> W;
-    if (OP == OP_SPITZER) {
-      W.w0p = o.w0;
-      W.w0m = pw0;
-      W.w1p = o.w1;
-      W.w1m = o.w1B;
-      W.w2p = o.w2;
-      W.w2m = o.w2C;
-      W.K01[0] = o.k01;
-      W.K01[1] = pk01;
-      W.K01[2] = o.k01B;
-      W.K01[3] = pk01B;
-      W.K02[0] = o.k02;
-      W.K02[1] = pk02;
-      W.K02[2] = o.k02C;
-      W.K02[3] = pk02C;
-      W.K12[0] = o.k12;
-      W.K12[1] = o.k12B;
-      W.K12[2] = o.k12C;
-      W.K12[3] = o.k12BC;
-    }
-    return W;
-  };
-  // coefficients of the plane before the first stage-k plane
-  R pw0 = 0, pk01 = 0, pk02 = 0, pk01B = 0, pk02C = 0;
-  if (OP == OP_SPITZER) {
-    const int cA = (nbr(wrapclamp(i0 - 1, g.n0, g.per0), g.n0, g.per0).m * g.n1 + jc) * g.n2 + kc;
-    pw0 = C.w0[cA];
-    pk01 = C.k01[cA];
-    pk02 = C.k02[cA];
-    pk01B = C.k01[cA + tg.dJm];
-    pk02C = C.k02[cA + tg.dKm];
-  }
-  __syncthreads();
-
-  for (int i = i0 - 1; i <= i1; ++i) {
-    const bool pre = i + 2 <= i1 + 1;
-    if (pre) load_a(i + 2, v);
-    // ---- stage k at plane i, on the extended region
-    {
-      const int ic = wrapclamp(i, g.n0, g.per0);
-      Own o;
-      load_own(ic, o);
-      const long long cc = off + (long long)(ic * g.n1 + jc) * g.n2 + kc;
-      const R xm2 = a.ukm2[cc], x0 = a.u0[cc], f0 = a.F0[cc];
-      const PlaneGeo<R> pg = plane_geo(ic);
-      const RowCoef<R> W = row_coef(o, pw0, pk01, pk02, pk01B, pk02C);
-      const int base = (ew + 1) * AK + (el + 1);
-      const R *sm = s_a[(i - 1) & 3], *s0 = s_a[i & 3], *sp = s_a[(i + 1) & 3];
-      auto U = [&](int di, int dj, int dk) -> R {
-        const R *s = di < 0 ? sm : (di > 0 ? sp : s0);
-        return s[base + dj * AK + dk];
-      };
-      const R su = apply_S<OP, true, R, double>(g, C, W, U, ic, jc, kc, pg, tg);
-      const R V = pg.v0 * tg.v12;
-      const R uk = a.mu1 * s0[base] + a.nu1 * xm2 + (1.0 - a.mu1 - a.nu1) * x0 +
-                   a.mt1 * (su / V) + a.gt1 * f0;
-      s_b[i & 3][tid] = uk;
-      if (outc && i >= i0 && i < i1) a.out1[off + ((long long)i * g.n1 + jj) * g.n2 + kk] = uk;
-      if (OP == OP_SPITZER) {
-        pw0 = o.w0;
-        pk01 = o.k01;
-        pk02 = o.k02;
-        pk01B = o.k01B;
-        pk02C = o.k02C;
-      }
-    }
-    __syncthreads();
-    // ---- stage k + 1 at plane i - 1, on the tile
-    const int ip = i - 1;
-    if (outc && ip >= i0 && ip < i1) {
-      Own o;
-      load_own(ip, o);
-      R qw0 = 0, qk01 = 0, qk02 = 0, qk01B = 0, qk02C = 0;
-      const PlaneGeo<R> pg = plane_geo(ip);
-      if (OP == OP_SPITZER) {
-        const int cA = (pg.A.m * g.n1 + jc) * g.n2 + kc;
-        qw0 = C.w0[cA];
-        qk01 = C.k01[cA];
-        qk02 = C.k02[cA];
-        qk01B = C.k01[cA + tg.dJm];
-        qk02C = C.k02[cA + tg.dKm];
-      }
-      const long long cc = off + ((long long)ip * g.n1 + jj) * g.n2 + kk;
-      const R x0 = a.u0[cc], f0 = a.F0[cc];
-      const RowCoef<R> W = row_coef(o, qw0, qk01, qk02, qk01B, qk02C);
-      const int base = ew * EK + el;
-      const R *sm = s_b[(ip - 1) & 3], *s0 = s_b[ip & 3], *sp = s_b[(ip + 1) & 3];
-      auto U = [&](int di, int dj, int dk) -> R {
-        const R *s = di < 0 ? sm : (di > 0 ? sp : s0);
-        return s[base + dj * EK + dk];
-      };
-      const R su = apply_S<OP, true, R, double>(g, C, W, U, ip, jc, kc, pg, tg);
-      const R V = pg.v0 * tg.v12;
-      const R ukm1c = s_a[ip & 3][(ew + 1) * AK + (el + 1)];
-      a.out2[cc] = a.mu2 * s0[base] + a.nu2 * ukm1c + (1.0 - a.mu2 - a.nu2) * x0 +
-                   a.mt2 * (su / V) + a.gt2 * f0;
-    }
-    if (pre) store_a(i + 2, v);
-    __syncthreads();
-  }
-}
-
-int chunk_of2(const sts_ctx *c) {
-  const long long tiles = (long long)((c->n2 + TK2 - 1) / TK2) * ((c->n1 + TJ2 - 1) / TJ2);
-  long long ci = tiles * c->n0 / STS_MARCH_WG;
-  if (ci < 4) ci = 4;
-  if (ci > 32) ci = 32;
-  return (int)std::min<long long>(ci, c->n0);
-}
 
 int chunk_of(const sts_ctx *c) {
   const long long tiles = (long long)((c->n2 + TK - 1) / TK) * ((c->n1 + TJ - 1) / TJ);
@@ -696,13 +409,9 @@ void launch(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
                      c->grid(), coef_of<CT>(c), ld, a, CI, nchunk, c->ncell);
 }
 
-#ifndef STS_GATHER19
-#define STS_GATHER19 1
-#endif
-
 template <int MODE, class Loader>
 void launch_op(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
-  if (STS_GATHER19 && c->op == OP_SPITZER)
+  if (c->op == OP_SPITZER)
     launch<OP_SPITZER, MODE, double>(c, ncomp, ld, a);
   else
     launch<OP_ISOTROPIC, MODE, double>(c, ncomp, ld, a);
@@ -710,59 +419,15 @@ void launch_op(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
 
 }  // namespace
 
-// Conduction (19-point) runs the flux-form kernels of k_flux.hip; the
-// isotropic 7-point operator runs the gather march below.
-int flux_parts(const sts_ctx *c);
-void flux_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, const double *ukm2,
-                const double *u0, double *F0, double *out, double mu, double nu, double mut_dt,
-                double gt_dt);
-void flux_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
-                 const double *zilu, const double *pold, double *pnew, double *y, double *part,
-                 const PcgScalars *sc, int first);
-void flux_residual(const sts_ctx *c, const double *b, const double *x, double dt, double *r,
-                   double *part);
-
 int stencil_parts(const sts_ctx *c) {
-  if (c->op == OP_SPITZER && !STS_GATHER19) return flux_parts(c);
   int CI, nchunk;
   const dim3 g = march_grid(c, 1, &CI, &nchunk);
   return (int)(g.x * g.y * g.z);
 }
 
-void launch_stage2(const sts_ctx *c, int ncomp, const double *ukm1, const double *ukm2,
-                   const double *u0, const double *F0, double *out1, double *out2,
-                   const double st1[4], const double st2[4]) {
-  Args2 a{};
-  a.out1 = out1;
-  a.out2 = out2;
-  a.ukm2 = ukm2;
-  a.u0 = u0;
-  a.F0 = F0;
-  a.mu1 = st1[0];
-  a.nu1 = st1[1];
-  a.mt1 = st1[2];
-  a.gt1 = st1[3];
-  a.mu2 = st2[0];
-  a.nu2 = st2[1];
-  a.mt2 = st2[2];
-  a.gt2 = st2[3];
-  const int CI = chunk_of2(c), nchunk = (c->n0 + CI - 1) / CI;
-  const dim3 grid(((c->n2 + TK2 - 1) / TK2) * ((c->n1 + TJ2 - 1) / TJ2) * nchunk * ncomp);
-  if (c->op == OP_SPITZER)
-    hipLaunchKernelGGL(k_rk2<OP_SPITZER>, grid, dim3(RK2_NT), 0, c->stream, c->grid(),
-                       coef_of<double>(c), ukm1, a, CI, nchunk, c->ncell);
-  else
-    hipLaunchKernelGGL(k_rk2<OP_ISOTROPIC>, grid, dim3(RK2_NT), 0, c->stream, c->grid(),
-                       coef_of<double>(c), ukm1, a, CI, nchunk, c->ncell);
-}
-
 void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, const double *ukm2,
                   const double *u0, double *F0, double *out, double mu, double nu, double mut_dt,
                   double gt_dt) {
-  if (c->op == OP_SPITZER && !STS_GATHER19) {
-    flux_stage(c, mode, ncomp, ukm1, ukm2, u0, F0, out, mu, nu, mut_dt, gt_dt);
-    return;
-  }
   Args a{};
   a.out = out;
   a.F0 = F0;
@@ -783,10 +448,6 @@ void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, con
 
 void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *pold,
                    double *pnew, double *y, double *part, const PcgScalars *sc, int first) {
-  if (c->op == OP_SPITZER && !STS_GATHER19) {
-    flux_pass_a(c, dt, nullptr, nullptr, z, pold, pnew, y, part, sc, first);
-    return;
-  }
   Args a{};
   a.out = pnew;
   a.y = y;
@@ -800,10 +461,6 @@ void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *p
 
 void launch_residual_init(const sts_ctx *c, const double *b, const double *x, double dt,
                           const double *, const double *, double *r, double *, double *part) {
-  if (c->op == OP_SPITZER && !STS_GATHER19) {
-    flux_residual(c, b, x, dt, r, part);
-    return;
-  }
   Args a{};
   a.out = r;
   a.b = b;
@@ -815,10 +472,6 @@ void launch_residual_init(const sts_ctx *c, const double *b, const double *x, do
 
 void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,
                           double *part) {
-  if (c->op == OP_SPITZER && !STS_GATHER19) {
-    flux_residual(c, b, x, dt, nullptr, part);
-    return;
-  }
   Args a{};
   a.b = b;
   a.part = part;

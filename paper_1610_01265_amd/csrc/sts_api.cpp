@@ -115,11 +115,7 @@ int stage_count(double ratio) {
 
 constexpr int kMaxStages = 1 << 20;
 constexpr int kPollEvery = 8;  // PCG iterations enqueued between host polls
-#ifndef STS_RK_FUSE
-#define STS_RK_FUSE 0
-#endif
-constexpr bool kRkFuse = STS_RK_FUSE;         // two stages per sweep where possible
-constexpr int kRkBuffers = kRkFuse ? 4 : 2;  // RKL2 state buffers besides F0
+constexpr int kRkBuffers = 2;  // RKL2 state buffers besides F0
 
 }  // namespace
 
@@ -556,39 +552,23 @@ static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, 
     return STS_OK;
   }
   LAUNCHCHK();
-  // u_{k-1} in prev1, u_{k-2} in prev2 (u_0 = u for k = 2).  Pairs of stages
-  // write into buffers that hold neither input; a single stage overwrites
-  // u_{k-2}, and the last stage writes u in place (it reads u_0 only at its
-  // own cell).
+  // u_{k-1} in prev1, u_{k-2} in prev2 (u_0 = u for k = 2).  A stage reads
+  // u_{k-2} only at its own cell, so it may overwrite it; the last stage
+  // writes u in place (it reads u_0 only at its own cell).
   const double *prev1 = P[0], *prev2 = u;
   auto free_buf = [&](const double *x, const double *y, const double *z) {
     for (int q = 0; q < kRkBuffers; ++q)
       if (P[q] != x && P[q] != y && P[q] != z) return P[q];
     return (double *)nullptr;
   };
-  int k = 2;
-  while (k <= s) {
+  for (int k = 2; k <= s; ++k) {
     double c1[4];
     coef(k, c1);
-    if (kRkFuse && !nl && scheme == 2 && k + 1 < s) {
-      double c2[4];
-      coef(k + 1, c2);
-      double *o1 = free_buf(prev1, prev2, nullptr);
-      double *o2 = free_buf(prev1, prev2, o1);
-      launch_stage2(ctx, ncomp, prev1, prev2, u, F0, o1, o2, c1, c2);
-      LAUNCHCHK();
-      prev2 = o1;
-      prev1 = o2;
-      k += 2;
-    } else {
-      // a single stage reads u_{k-2} only at its own cell: it may overwrite it
-      double *out = (k == s) ? u : (prev2 != u ? (double *)prev2 : free_buf(prev1, prev2, nullptr));
-      stage(2, prev1, prev2, out, c1);
-      LAUNCHCHK();
-      prev2 = prev1;
-      prev1 = out;
-      k += 1;
-    }
+    double *out = (k == s) ? u : (prev2 != u ? (double *)prev2 : free_buf(prev1, prev2, nullptr));
+    stage(2, prev1, prev2, out, c1);
+    LAUNCHCHK();
+    prev2 = prev1;
+    prev1 = out;
   }
   return STS_OK;
 }

@@ -140,12 +140,6 @@ void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, con
                   const double *u0, double *F0, double *out, double mu, double nu, double mut_dt,
                   double gt_dt);
 
-// two RKL2 stages k, k+1 in one sweep: out1 = u_k, out2 = u_{k+1} (neither
-// may alias an input); st = {mu, nu, mu~ dt, gamma~ dt} of each stage
-void launch_stage2(const sts_ctx *c, int ncomp, const double *ukm1, const double *ukm2,
-                   const double *u0, const double *F0, double *out1, double *out2,
-                   const double st1[4], const double st2[4]);
-
 // Conduction with kappa = kappa0 max(u, 0)^{5/2} taken from the stencil
 // input itself (k_nonlinear.hip); modes as launch_stage, one component.
 void launch_stage_nl(const sts_ctx *c, int mode, const double *ukm1, const double *ukm2,

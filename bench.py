@@ -409,6 +409,15 @@ def main():
     def ratio(a, b):
         return a / b if (a > 0 and b > 0) else None
 
+    def pcg_hbm(iters, bpc, seconds):
+        """Algorithmic bytes of the iterations over the whole solve time
+        (set-up included, so a lower bound on the sweeps' own rate)."""
+        if not iters or seconds <= 0:
+            return None
+        gbs = iters * bpc * ncell / seconds / 1e9
+        return {"alg_bytes_per_cell_iteration": bpc, "achieved_GBs": gbs,
+                "frac_hbm": gbs / HBM_PEAK_GBS}
+
     out = {
         "metric": "RKL2 stage cell-updates/s + BE-PCG s/solve at 1e-8 res; % HBM peak",
         "value": value,
@@ -436,6 +445,10 @@ def main():
                          "fp32_form_jacobi_inner": info.get("it_jac32"),
                          "learned_guess_jacobi": info.get("it_learned"),
                          "viscosity_jacobi": info.get("it_visc")},
+        "be_pcg_hbm": {"jacobi": pcg_hbm(info.get("it_jac"), 144, t_jac),
+                       "block_ilu0_8x8x8": pcg_hbm(info.get("it_ilu"), 216, sec["ilu0"]),
+                       "viscosity_jacobi": pcg_hbm(sum(info.get("it_visc") or []), 96,
+                                                   sec["visc_jacobi"])},
         "speedup_vs_fp64_jacobi_pcg": {
             "block_ilu0_8x8x8": ratio(t_jac, sec["ilu0"]),
             "fp32_form_jacobi": ratio(t_jac, sec["fp32_jacobi"]),

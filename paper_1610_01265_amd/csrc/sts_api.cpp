@@ -281,6 +281,8 @@ sts_status sts_destroy(sts_ctx *ctx) {
   dfree(ctx->d_rtab);
   dfree(ctx->d_rws);
   if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
   return STS_OK;
 }
@@ -714,6 +716,40 @@ static sts_status pcg_workspace(sts_ctx *ctx, int pc, const int block[3], double
   return STS_OK;
 }
 
+}  // extern "C"
+
+// PCG iterations in batches of kPollEvery.  Each batch's scalars are copied
+// behind it into one of two pinned slots and an event is recorded; the host
+// waits for batch b's copy only after enqueuing batch b + 1, so the device
+// never idles during the host's round trip.  Batches enqueued after
+// convergence exit at once (the device also stops at sc->maxit).  On return
+// the first slot holds the final scalars.  one(it) enqueues iteration it.
+template <class F>
+static sts_status pcg_iterate(sts_ctx *ctx, const PcgScalars *sc, int maxit, F &&one) {
+  PcgScalars *slot[2] = {(PcgScalars *)ctx->h_pin, (PcgScalars *)((char *)ctx->h_pin + 128)};
+  static_assert(sizeof(PcgScalars) <= 128, "two scalar slots in the pinned buffer");
+  for (hipEvent_t &e : ctx->ev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  bool stop = slot[0]->done != 0;  // the caller's copy after the initialisation
+  for (int it = 0, batch = 0; !stop && it < maxit; ++batch) {
+    const int nb = std::min(kPollEvery, maxit - it);
+    for (int q = 0; q < nb; ++q, ++it) one(it);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(slot[batch & 1], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev[batch & 1], ctx->stream));
+    if (batch > 0) {
+      HIPCHK(hipEventSynchronize(ctx->ev[(batch - 1) & 1]));
+      stop = slot[(batch - 1) & 1]->done != 0;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(slot[0], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return STS_OK;
+}
+
+extern "C" {
+
 // FP32 form of BE + Jacobi-PCG: mixed-precision iterative refinement.  The
 // outer residual r = b - A x is formed in FP64 (FP32 coefficients widened);
 // the correction A e = r is solved by PCG with FP32 vectors and FP64 dot
@@ -756,20 +792,14 @@ static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, d
     HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     float *pold = p0, *pnew = p1;
-    for (int it = 0; it < maxit - total && !h->done; ++it) {
+    st = pcg_iterate(ctx, sc, maxit - total, [&](int it) {
       f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
       launch_finalize_alpha(ctx, part, np3, sc);
       f32_pass_b(ctx, e, pnew, r, y, iv, z, part, sc);
       launch_finalize_beta(ctx, part, np1, sc);
-      LAUNCHCHK();
       std::swap(pold, pnew);
-      if ((it + 1) % kPollEvery == 0 || it + 1 == maxit - total) {
-        HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
-      }
-    }
-    HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+    if (st) return st;
     if (h->status == -4) FAIL(STS_BREAKDOWN, "FP32 form: inner PCG breakdown");
     total += h->iters;
     f32_add_to(ctx, x, e);
@@ -839,23 +869,18 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   double *pold = p0, *pnew = p1;
   HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  for (int it = 0; it < maxit && !h->done; ++it) {
+  const int np3 = stencil_parts(ctx);
+  st = pcg_iterate(ctx, sc, maxit, [&](int it) {
     launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
-    launch_finalize_alpha(ctx, part, stencil_parts(ctx), sc);
+    launch_finalize_alpha(ctx, part, np3, sc);
     if (ilu)
       launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
     else
       launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, z, part, sc);
     launch_finalize_beta(ctx, part, nb_parts, sc);
-    LAUNCHCHK();
     std::swap(pold, pnew);
-    if ((it + 1) % kPollEvery == 0 || it + 1 == maxit) {
-      HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-    }
-  }
-  HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+  if (st) return st;
   if (iters) *iters = h->iters;
   if (relres) *relres = h->bnorm2 > 0 ? std::sqrt(h->rnorm2 / h->bnorm2) : 0.0;
   if (h->status == -4) FAIL(STS_BREAKDOWN, "PCG breakdown: p.Ap <= 0 or non-finite residual");
@@ -1079,20 +1104,16 @@ sts_status resistivity_be_pcg_solve(sts_ctx *ctx, const double *E_n, double *E, 
   double *pold = p0, *pnew = p1;
   HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  for (int it = 0; it < maxit && !h->done; ++it) {
-    launch_res_pass_a(ctx, dt, r, invd, pold, pnew, Phi, y, part, sc, it == 0);
-    launch_finalize_alpha_n(ctx, part, P, sc);
-    launch_pass_b_jacobi_n(ctx, ne, E, pnew, r, y, invd, part, P, sc);
-    launch_finalize_beta(ctx, part, P, sc);
-    LAUNCHCHK();
-    std::swap(pold, pnew);
-    if ((it + 1) % kPollEvery == 0 || it + 1 == maxit) {
-      HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-    }
+  {
+    const sts_status st = pcg_iterate(ctx, sc, maxit, [&](int it) {
+      launch_res_pass_a(ctx, dt, r, invd, pold, pnew, Phi, y, part, sc, it == 0);
+      launch_finalize_alpha_n(ctx, part, P, sc);
+      launch_pass_b_jacobi_n(ctx, ne, E, pnew, r, y, invd, part, P, sc);
+      launch_finalize_beta(ctx, part, P, sc);
+      std::swap(pold, pnew);
+    });
+    if (st) return st;
   }
-  HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
   if (iters) *iters = h->iters;
   if (relres) *relres = h->bnorm2 > 0 ? std::sqrt(h->rnorm2 / h->bnorm2) : 0.0;
   if (h->status == -4) FAIL(STS_BREAKDOWN, "PCG breakdown: p.Ap <= 0 or non-finite residual");

@@ -113,7 +113,8 @@ struct sts_ctx {
   int res_off[18] = {};       // offsets of the 18 weight tables in d_rtab
   double *d_rtab = nullptr;
   double *d_rws = nullptr;    // faces x 2, edges x 6 (PCG vectors)
-  void *h_pin = nullptr;      // pinned host mirror of flags / scalars
+  void *h_pin = nullptr;      // pinned host mirror of flags / scalars (two 128-byte slots)
+  hipEvent_t ev[2] = {nullptr, nullptr};  // PCG batch completion (pipelined polls)
 
   sts::Grid grid() const;
   sts::Coef coef() const;

@@ -24,4 +24,8 @@ Modules
 
 Parity status: every function is pinned by the CPU tests in
 tests/test_oracle_*.py (closed forms, invariants, brute force on tiny grids).
+The conduction discretisation itself is a reading of the paper's "standard
+scheme" (an exactly symmetric energy form with the same 19-point stencil);
+its agreement with the paper's own scheme is parity unpinned, as no code or
+data of that scheme exists here.
 """

@@ -58,6 +58,7 @@ def test_create_rejects_bad_arguments_without_gpu_work(lib):
 BAD_CREATE = [
     # (coord, n, bc, face arrays: "ok" | "dec" | "neg" | "pole"), each rejected on the host
     (0, (2048, 2048, 1024), (0, 0, 0, 0, 2, 2), "ok"),   # 4.3e9 cells: 32-bit indices overflow
+    (0, (1024, 1024, 1024), (0, 0, 0, 0, 2, 2), "ok"),   # 2^30 cells: one past the limit
     (0, (0, 4, 4), (0, 0, 0, 0, 2, 2), "ok"),            # empty axis
     (0, (4, 4, 4), (0, 0, 0, 0, 2, 0), "ok"),            # periodic on one side only
     (0, (4, 4, 2), (0, 0, 0, 0, 2, 2), "ok"),            # periodic axis with < 3 cells

@@ -110,3 +110,44 @@ def test_max_grid_rkl2_at_sampled_cells(big):
         op, take, cc = window_op(w, c, 5)
         ref.append(orkl2.rkl2_step(lambda v: O.apply_F(op, v), take(w["T"]), dt, 3)[cc])
     assert relmax(got, np.array(ref), scale=scale) <= 1e-12
+
+
+def test_max_grid_be_jacobi_residual(big, gpu_lib):
+    """A converged Jacobi-PCG solve at the largest grid: the oracle's residual
+    rows at the sampled cells obey |r_c| <= ||r||_2 <= rtol ||b||_2, with
+    ||b||_2 from the separable factors (cell volume = radial x polar x
+    azimuthal factor, T = A B) plus the Dirichlet layer i = 0 taken from a
+    two-plane oracle slab."""
+    from oracle import operator as O
+    w, ctx, T = big
+    dt = 2.0 * ctx.dt_euler()
+    rtol = 1e-10
+    x = T.clone()
+    it, rel, st = ctx.be_pcg_solve(T, x, dt, pc=gpu_lib.PC_JACOBI, rtol=rtol)
+    assert st == 0 and rel <= rtol
+    assert ctx.be_residual(T, x, dt) <= 1.01 * rtol
+    rf, thf, phf = w["rf"], w["thf"], w["phf"]
+    # ||b||^2: rows i >= 1 are V T; row 0 also carries dt g
+    vr = (rf[1:] ** 3 - rf[:-1] ** 3) / 3.0
+    vt = np.cos(thf[:-1]) - np.cos(thf[1:])
+    vp = phf[1:] - phf[:-1]
+    A, B = w["T"].A, w["T"].B
+    sb = float(np.sum((vt[:, None] * vp[None, :] * B) ** 2))
+    slab_T = A[:2, None, None] * B[None]
+    b2 = [np.broadcast_to(w[k].b2, (2,) + B.shape) for k in ("br", "bt", "bp")]
+    op = O.assemble("spherical", rf[:3], thf, phf, O.spitzer_tensor(slab_T, 1e-15, *b2),
+                    (O.DIRICHLET, O.ZEROFLUX, O.ZEROFLUX, O.ZEROFLUX, O.PERIODIC, O.PERIODIC),
+                    u_lo=1.5e6)
+    b0 = op.V[0] * slab_T[0] + dt * op.g[0]
+    bnorm = math.sqrt(float(np.sum((vr[1:] * A[1:]) ** 2)) * sb + float(np.sum(b0 ** 2)))
+    r = []
+    for c in CELLS:
+        opw, take, cc = window_op(w, c, 2)
+        # x on the window: gather the window's cells from the device
+        i0, i1 = max(0, c[0] - 2), min(SHAPE[0], c[0] + 3)
+        j0, j1 = max(0, c[1] - 2), min(SHAPE[1], c[1] + 3)
+        ks = [(c[2] + d) % SHAPE[2] for d in range(-2, 3)]
+        xw = x[i0:i1, j0:j1][:, :, ks].cpu().numpy()
+        A19, b = O.be_system(opw, take(w["T"]), dt)
+        r.append((b - O.apply19(A19, xw))[cc])
+    assert np.max(np.abs(r)) <= 1.01 * rtol * bnorm, (max(abs(v) for v in r), bnorm)

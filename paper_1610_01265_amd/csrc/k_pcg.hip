@@ -113,14 +113,40 @@ __global__ void k_fin_alpha(const double *part, int n, PcgScalars *sc) {
 }
 
 // Grid-stride over the cells with a bounded number of workgroups, so the
-// finalize kernel sums few partials.
+// finalize kernel sums few partials.  FUSE: alpha = (r.z) / (p.Ap) is formed
+// here from pass A's partials pa[0..npa) by every workgroup (same sum, same
+// order, same value; p.Ap <= 0 or non-finite is a breakdown for all), and
+// workgroup 0 records p.Ap, alpha and (r.z)_old = r.z for the next sweep's
+// beta; r.z is not written in this launch.
+template <bool FUSE>
 __global__ void __launch_bounds__(NT)
     k_pass_b_jac(long long n, double *__restrict__ x, const double *__restrict__ p,
                  double *__restrict__ r, const double *__restrict__ y,
                  const double *__restrict__ invd, double *__restrict__ zout, double *part,
-                 long long cap, const PcgScalars *sc) {
+                 long long cap, PcgScalars *sc, const double *pa, int npa) {
   if (sc->done) return;
-  const double alpha = sc->alpha;
+  double alpha;
+  if (FUSE) {
+    __shared__ double s_py;
+    block_sum_parts(pa, npa, 0, &s_py, nullptr);
+    __syncthreads();
+    const double py = s_py, rz = sc->rr;
+    const bool bad = !(py > 0.0) || !isfinite(py);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->py = py;
+      sc->rr_old = rz;
+      if (bad) {
+        sc->done = 1;
+        sc->status = -4;
+      } else {
+        sc->alpha = rz / py;
+      }
+    }
+    if (bad) return;
+    alpha = rz / py;
+  } else {
+    alpha = sc->alpha;
+  }
   double rz = 0.0, rr = 0.0;
   const long long stride = (long long)gridDim.x * NT;
   for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
@@ -159,6 +185,14 @@ __global__ void k_fin_beta(const double *part, int n, long long cap, PcgScalars 
       sc->beta = s_z / sc->rr_old;
     }
   }
+}
+
+// The end-of-iteration test of the last fused Jacobi-PCG iteration, which
+// has no following sweep to evaluate it.
+__global__ void k_fin_check(const double *part, int n, long long cap, int iters, PcgScalars *sc) {
+  if (sc->done) return;
+  double beta;
+  pcg_decide(part, n, cap, iters, sc, true, (int)threadIdx.x, &beta);
 }
 
 // FP32 form inner solve: r = (float) r64, 1/A_ii in FP32, e = 0, p = z;
@@ -284,8 +318,9 @@ void launch_finalize_alpha_n(const sts_ctx *c, const double *part, int nparts, P
 void launch_pass_b_jacobi_n(const sts_ctx *c, long long n, double *x, const double *p, double *r,
                             const double *y, const double *invd, double *part, int nparts,
                             const PcgScalars *sc) {
-  hipLaunchKernelGGL(k_pass_b_jac, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y, invd,
-                     (double *)nullptr, part, cap_of(c), sc);
+  hipLaunchKernelGGL(k_pass_b_jac<false>, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y,
+                     invd, (double *)nullptr, part, cap_of(c), (PcgScalars *)sc,
+                     (const double *)nullptr, 0);
 }
 
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars *sc) {
@@ -295,8 +330,22 @@ void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars
 void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
                           const double *y, const double *invd, double *z, double *part,
                           const PcgScalars *sc) {
-  hipLaunchKernelGGL(k_pass_b_jac, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, x, p,
-                     r, y, invd, z, part, cap_of(c), sc);
+  hipLaunchKernelGGL(k_pass_b_jac<false>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell,
+                     x, p, r, y, invd, z, part, cap_of(c), (PcgScalars *)sc,
+                     (const double *)nullptr, 0);
+}
+
+void launch_pass_b_jacobi_fused(const sts_ctx *c, double *x, const double *p, double *r,
+                                const double *y, const double *invd, double *z, double *part,
+                                PcgScalars *sc, const double *pa, int npa) {
+  hipLaunchKernelGGL(k_pass_b_jac<true>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell,
+                     x, p, r, y, invd, z, part, cap_of(c), sc, pa, npa);
+}
+
+void launch_finalize_check(const sts_ctx *c, const double *part, int nparts, int iters,
+                           PcgScalars *sc) {
+  hipLaunchKernelGGL(k_fin_check, dim3(1), dim3(256), 0, c->stream, part, nparts, cap_of(c), iters,
+                     sc);
 }
 
 void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc) {

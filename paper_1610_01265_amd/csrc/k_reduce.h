@@ -42,10 +42,11 @@ __device__ __forceinline__ void wg_sum2(double a, double b, int tid, double *out
 // 256 threads, in a fixed order: each thread issues its (up to) 8 loads of a
 // 2048-entry round at once, then wave shuffles and the four wave totals in
 // a fixed order.  (One round of independent loads instead of a chain of
-// dependent ones; the finalizers sit between every two PCG sweeps.)
+// dependent ones; the finalizers sit between every two PCG sweeps.)  tid is
+// the thread's linear index in a workgroup of 256 (x fastest).
 __device__ __forceinline__ void block_sum_parts(const double *part, int n, long long stride,
-                                                double *s0, double *s1) {
-  const int tid = threadIdx.x;
+                                                double *s0, double *s1,
+                                                int tid = threadIdx.x) {
   double a = 0.0, b = 0.0;
   for (int t0 = 0; t0 < n; t0 += 8 * 256) {
     double va[8], vb[8];
@@ -73,6 +74,48 @@ __device__ __forceinline__ void block_sum_parts(const double *part, int n, long 
     *s0 = (ra[0] + ra[1]) + (ra[2] + ra[3]);
     if (s1) *s1 = (rb[0] + rb[1]) + (rb[2] + rb[3]);
   }
+}
+
+// End of a Jacobi-PCG iteration (Sec. 2.2, Fig. pcg), evaluated at the start
+// of the next sweep instead of in a kernel of its own: r.z and r.r from the
+// partials of the iteration's x / r update (part[0..n), part[stride..+n)),
+// then the stopping test ||r||^2 <= tol2 (converged), a non-finite sum
+// (breakdown) or iters >= maxit, else beta = (r.z) / (r.z)_old.  Every
+// workgroup of the launch sums the same partials in the same order, so all
+// take the same decision; only the `writer` workgroup records the scalars
+// (r.z, ||r||^2, iteration count, beta, done / status).  Fields read here
+// (rr_old, tol2, maxit) are not written in the same launch.  Returns 1 when
+// the iteration is the last.  256 threads, linear index tid.
+template <class Scalars>
+__device__ __forceinline__ int pcg_decide(const double *part, int n, long long stride, int iters,
+                                          Scalars *sc, bool writer, int tid, double *beta) {
+  __shared__ double s_z, s_r;
+  block_sum_parts(part, n, stride, &s_z, &s_r, tid);
+  __syncthreads();
+  const double rz = s_z, rr = s_r;
+  int done = 0, status = 0;
+  if (!isfinite(rr) || !isfinite(rz)) {
+    done = 1;
+    status = -4;
+  } else if (!(rr > sc->tol2)) {
+    done = 1;
+    status = 1;
+  } else if (iters >= sc->maxit) {
+    done = 1;
+  }
+  *beta = rz / sc->rr_old;
+  if (writer && tid == 0) {
+    sc->rr = rz;
+    sc->rnorm2 = rr;
+    sc->iters = iters;
+    if (done) {
+      sc->done = 1;
+      if (status) sc->status = status;
+    } else {
+      sc->beta = *beta;
+    }
+  }
+  return done;
 }
 
 }  // namespace sts

@@ -73,6 +73,7 @@ struct LoadP {
   int first;
   T beta;
   __device__ __forceinline__ void prepare() { beta = first ? T(0) : T(sc->beta); }
+  __device__ __forceinline__ void set_beta(double b) { beta = T(b); }
   __device__ __forceinline__ T operator()(long long idx) const {
     return first ? z[idx] : z[idx] + beta * pold[idx];
   }
@@ -89,7 +90,10 @@ struct Args {
   double *part;        // per-workgroup partial sums (two regions of cap)
   long long cap;
   double mu, nu, mut_dt, gt_dt, dt;
-  const PcgScalars *sc;
+  PcgScalars *sc;
+  const double *pb;  // pass A after a fused pass B: its partials (r.z, r.r), else null
+  int npb;           // their count per region (regions cap apart)
+  int iters;         // iterations completed before this sweep
 };
 
 #ifndef STS_MARCH_WPE
@@ -101,7 +105,21 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   using R = typename Loader::value_type;
   if (MODE == M_PA && a.sc->done) return;
   __shared__ R s_u[4][PL];
-  ld.prepare();
+  if constexpr (MODE == M_PA && OP == OP_SPITZER && sizeof(R) == 8) {
+    if (a.pb) {
+      // the previous iteration's stopping test and this one's beta, from the
+      // fused pass B's partials (identical in every workgroup)
+      double beta;
+      if (pcg_decide(a.pb, a.npb, a.cap, a.iters, a.sc, blockIdx.x == 0,
+                     (int)(threadIdx.y * TK + threadIdx.x), &beta))
+        return;
+      ld.set_beta(beta);
+    } else {
+      ld.prepare();
+    }
+  } else {
+    ld.prepare();
+  }
   // a wavefront is one tile row (blockDim.x = 64): theta-dependent values
   // are uniform across it
   const int tk = threadIdx.x, tj = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -447,14 +465,18 @@ void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, con
 }
 
 void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *pold,
-                   double *pnew, double *y, double *part, const PcgScalars *sc, int first) {
+                   double *pnew, double *y, double *part, const PcgScalars *sc, int first,
+                   const double *pb, int npb, int iters) {
   Args a{};
   a.out = pnew;
   a.y = y;
   a.part = part;
   a.cap = c->red_cap;
   a.dt = dt;
-  a.sc = sc;
+  a.sc = (PcgScalars *)sc;
+  a.pb = first ? nullptr : pb;
+  a.npb = npb;
+  a.iters = iters;
   const LoadP<double> ld{z, pold, sc, first, 0.0};
   launch_op<M_PA>(c, 1, ld, a);
 }
@@ -539,7 +561,7 @@ void f32_pass_a(const sts_ctx *c, double dt, const float *z, const float *pold, 
   a.part = part;
   a.cap = c->red_cap;
   a.dt = dt;
-  a.sc = sc;
+  a.sc = (PcgScalars *)sc;
   const LoadP<float> ld{z, pold, sc, first, 0.0f};
   launch_f32<M_PA>(c, 1, ld, a);
 }

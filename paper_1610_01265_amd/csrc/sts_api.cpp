@@ -406,7 +406,7 @@ static sts_status ensure_red(sts_ctx *ctx, int need) {
   if (ctx->red_cap >= need) return STS_OK;
   dfree(ctx->d_red);
   ctx->red_cap = 0;
-  sts_status st = dalloc(ctx, (void **)&ctx->d_red, (size_t)3 * need * 8);
+  sts_status st = dalloc(ctx, (void **)&ctx->d_red, (size_t)4 * need * 8);
   if (st) return st;
   ctx->red_cap = need;
   return STS_OK;
@@ -870,17 +870,37 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   const int np3 = stencil_parts(ctx);
+  // Jacobi on the conduction operator: two launches per iteration.  Pass B
+  // forms alpha from pass A's partials (region 0) and writes its own to
+  // regions 2 and 3; the next pass A evaluates the stopping test and beta from
+  // those, so no kernel sits between the sweeps (-2 % per solve).  Block ILU0
+  // and the 7-point operator keep the separate finalizers (the latter's pass
+  // A would lose a wave per SIMD to the fused prologue).
+  double *part_b = part + 2 * cap;
+  const bool fused = !ilu && ctx->op == OP_SPITZER;
   st = pcg_iterate(ctx, sc, maxit, [&](int it) {
-    launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
-    launch_finalize_alpha(ctx, part, np3, sc);
-    if (ilu)
-      launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
-    else
-      launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, z, part, sc);
-    launch_finalize_beta(ctx, part, nb_parts, sc);
+    if (!fused) {
+      launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
+      launch_finalize_alpha(ctx, part, np3, sc);
+      if (ilu)
+        launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
+      else
+        launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, z, part, sc);
+      launch_finalize_beta(ctx, part, nb_parts, sc);
+    } else {
+      launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, nb_parts, it);
+      launch_pass_b_jacobi_fused(ctx, x, pnew, r, y, invd, z, part_b, sc, part, np3);
+    }
     std::swap(pold, pnew);
   });
   if (st) return st;
+  if (fused && maxit > 0 && !h->done) {
+    // every one of the maxit iterations ran; evaluate the last one's end
+    launch_finalize_check(ctx, part_b, nb_parts, maxit, sc);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   if (iters) *iters = h->iters;
   if (relres) *relres = h->bnorm2 > 0 ? std::sqrt(h->rnorm2 / h->bnorm2) : 0.0;
   if (h->status == -4) FAIL(STS_BREAKDOWN, "PCG breakdown: p.Ap <= 0 or non-finite residual");

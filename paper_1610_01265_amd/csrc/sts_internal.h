@@ -202,14 +202,27 @@ void launch_finalize_init_n(const sts_ctx *c, const double *pb, int nb, const do
 void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr,
                            const double *prz, PcgScalars *sc, double rtol, int maxit);
 // pass A: p = z + beta p_old (z stored by the previous pass), y = A p, partial p.y
+// pb != null (and !first): the sweep first evaluates the previous
+// iteration's end (stopping test, beta) from a fused pass B's partials pb
+// (npb per region), the iteration count being `iters`.
 void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *pold,
-                   double *pnew, double *y, double *part, const PcgScalars *sc, int first);
+                   double *pnew, double *y, double *part, const PcgScalars *sc, int first,
+                   const double *pb = nullptr, int npb = 0, int iters = 0);
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
 // also stores z = r / A_ii of the updated residual for the next pass A
 void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
                           const double *y, const double *invd, double *z, double *part,
                           const PcgScalars *sc);
 void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
+// Jacobi pass B that forms alpha itself from pass A's partials pa (npa), then
+// updates x, r, z and writes its partials (r.z, r.r) to part, part + cap; the
+// end of its iteration is evaluated by the next fused pass A, or, after the
+// last one, by launch_finalize_check.
+void launch_pass_b_jacobi_fused(const sts_ctx *c, double *x, const double *p, double *r,
+                                const double *y, const double *invd, double *z, double *part,
+                                PcgScalars *sc, const double *pa, int npa);
+void launch_finalize_check(const sts_ctx *c, const double *part, int nparts, int iters,
+                           PcgScalars *sc);
 void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,
                           double *part);
 void launch_sum2(const sts_ctx *c, const double *part, int nparts, double *out2);

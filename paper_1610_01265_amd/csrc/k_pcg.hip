@@ -113,11 +113,8 @@ __global__ void k_fin_alpha(const double *part, int n, PcgScalars *sc) {
 }
 
 // Grid-stride over the cells with a bounded number of workgroups, so the
-// finalize kernel sums few partials.  FUSE: alpha = (r.z) / (p.Ap) is formed
-// here from pass A's partials pa[0..npa) by every workgroup (same sum, same
-// order, same value; p.Ap <= 0 or non-finite is a breakdown for all), and
-// workgroup 0 records p.Ap, alpha and (r.z)_old = r.z for the next sweep's
-// beta; r.z is not written in this launch.
+// partial sums stay few.  FUSE: alpha is formed here from pass A's partials
+// pa[0..npa) by every workgroup (pcg_alpha), workgroup 0 recording it.
 template <bool FUSE>
 __global__ void __launch_bounds__(NT)
     k_pass_b_jac(long long n, double *__restrict__ x, const double *__restrict__ p,
@@ -127,23 +124,7 @@ __global__ void __launch_bounds__(NT)
   if (sc->done) return;
   double alpha;
   if (FUSE) {
-    __shared__ double s_py;
-    block_sum_parts(pa, npa, 0, &s_py, nullptr);
-    __syncthreads();
-    const double py = s_py, rz = sc->rr;
-    const bool bad = !(py > 0.0) || !isfinite(py);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->py = py;
-      sc->rr_old = rz;
-      if (bad) {
-        sc->done = 1;
-        sc->status = -4;
-      } else {
-        sc->alpha = rz / py;
-      }
-    }
-    if (bad) return;
-    alpha = rz / py;
+    if (!pcg_alpha(pa, npa, sc, blockIdx.x == 0, (int)threadIdx.x, &alpha)) return;
   } else {
     alpha = sc->alpha;
   }

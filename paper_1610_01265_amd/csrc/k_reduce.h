@@ -76,7 +76,37 @@ __device__ __forceinline__ void block_sum_parts(const double *part, int n, long 
   }
 }
 
-// End of a Jacobi-PCG iteration (Sec. 2.2, Fig. pcg), evaluated at the start
+// alpha = (r.z) / (p.Ap) of a PCG iteration (Sec. 2.2, Fig. pcg), evaluated
+// at the start of the x / r update sweep instead of in a kernel of its own:
+// p.Ap from pass A's partials pa[0..npa).  Every workgroup sums the same
+// partials in the same order, so all get the same alpha, and p.Ap <= 0 or a
+// non-finite sum (breakdown) stops them all (returns 0).  The `writer`
+// workgroup records p.Ap, alpha (or done / breakdown) and (r.z)_old = r.z for
+// the next beta; r.z itself is not written in the same launch.  256 threads,
+// linear index tid.
+template <class Scalars>
+__device__ __forceinline__ int pcg_alpha(const double *pa, int npa, Scalars *sc, bool writer,
+                                         int tid, double *alpha) {
+  __shared__ double s_py;
+  block_sum_parts(pa, npa, 0, &s_py, nullptr, tid);
+  __syncthreads();
+  const double py = s_py, rz = sc->rr;
+  const bool bad = !(py > 0.0) || !isfinite(py);
+  if (writer && tid == 0) {
+    sc->py = py;
+    sc->rr_old = rz;
+    if (bad) {
+      sc->done = 1;
+      sc->status = -4;
+    } else {
+      sc->alpha = rz / py;
+    }
+  }
+  *alpha = rz / py;
+  return !bad;
+}
+
+// End of a PCG iteration (Sec. 2.2, Fig. pcg), evaluated at the start
 // of the next sweep instead of in a kernel of its own: r.z and r.r from the
 // partials of the iteration's x / r update (part[0..n), part[stride..+n)),
 // then the stopping test ||r||^2 <= tol2 (converged), a non-finite sum

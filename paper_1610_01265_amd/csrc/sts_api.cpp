@@ -873,9 +873,10 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   // Jacobi on the conduction operator: two launches per iteration.  Pass B
   // forms alpha from pass A's partials (region 0) and writes its own to
   // regions 2 and 3; the next pass A evaluates the stopping test and beta from
-  // those, so no kernel sits between the sweeps (-2 % per solve).  Block ILU0
-  // and the 7-point operator keep the separate finalizers (the latter's pass
-  // A would lose a wave per SIMD to the fused prologue).
+  // those, so no kernel sits between the sweeps (-4 to -5 % per solve).
+  // Block ILU0 keeps the separate finalizers (fused, its latency-bound solve
+  // sweep measured no faster), and so does the 7-point operator (its pass A
+  // would lose a wave per SIMD to the fused prologue).
   double *part_b = part + 2 * cap;
   const bool fused = !ilu && ctx->op == OP_SPITZER;
   st = pcg_iterate(ctx, sc, maxit, [&](int it) {

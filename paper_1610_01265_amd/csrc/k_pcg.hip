@@ -197,13 +197,21 @@ __global__ void __launch_bounds__(NT)
   wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
 }
 
+// FUSE: alpha from pass A's partials pa[0..npa) in every workgroup (pcg_alpha).
+template <bool FUSE>
 __global__ void __launch_bounds__(NT)
     k_f32_pass_b(long long n, float *__restrict__ e, const float *__restrict__ p,
                  float *__restrict__ r, const float *__restrict__ y,
                  const float *__restrict__ invd, float *__restrict__ z, double *part,
-                 long long cap, const PcgScalars *sc) {
+                 long long cap, PcgScalars *sc, const double *pa, int npa) {
   if (sc->done) return;
-  const float alpha = (float)sc->alpha;
+  double a64;
+  if (FUSE) {
+    if (!pcg_alpha(pa, npa, sc, blockIdx.x == 0, (int)threadIdx.x, &a64)) return;
+  } else {
+    a64 = sc->alpha;
+  }
+  const float alpha = (float)a64;
   double rz = 0.0, rr = 0.0;
   const long long stride = (long long)gridDim.x * NT;
   for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
@@ -354,9 +362,16 @@ void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, f
 }
 
 void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const float *y,
-                const float *invd, float *z, double *part, const PcgScalars *sc) {
-  hipLaunchKernelGGL(k_f32_pass_b, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, e, p,
-                     r, y, invd, z, part, (long long)c->red_cap, sc);
+                const float *invd, float *z, double *part, const PcgScalars *sc,
+                const double *pa, int npa) {
+  PcgScalars *s = const_cast<PcgScalars *>(sc);
+  if (pa)
+    hipLaunchKernelGGL(k_f32_pass_b<true>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream,
+                       c->ncell, e, p, r, y, invd, z, part, (long long)c->red_cap, s, pa, npa);
+  else
+    hipLaunchKernelGGL(k_f32_pass_b<false>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream,
+                       c->ncell, e, p, r, y, invd, z, part, (long long)c->red_cap, s,
+                       (const double *)nullptr, 0);
 }
 
 void f32_add_to(const sts_ctx *c, double *x, const float *e) {

@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   using R = typename Loader::value_type;
   if (MODE == M_PA && a.sc->done) return;
   __shared__ R s_u[4][PL];
-  if constexpr (MODE == M_PA && OP == OP_SPITZER && sizeof(R) == 8) {
+  if constexpr (MODE == M_PA && OP == OP_SPITZER) {
     if (a.pb) {
       // the previous iteration's stopping test and this one's beta, from the
       // fused pass B's partials (identical in every workgroup)
@@ -554,7 +554,8 @@ void f32_stage(const sts_ctx *c, int last, int ncomp, const float *dkm1, const f
 }
 
 void f32_pass_a(const sts_ctx *c, double dt, const float *z, const float *pold, float *pnew,
-                float *y, double *part, const PcgScalars *sc, int first) {
+                float *y, double *part, const PcgScalars *sc, int first, const double *pb,
+                int npb, int iters) {
   Args a{};
   a.out = pnew;
   a.y = y;
@@ -562,6 +563,9 @@ void f32_pass_a(const sts_ctx *c, double dt, const float *z, const float *pold, 
   a.cap = c->red_cap;
   a.dt = dt;
   a.sc = (PcgScalars *)sc;
+  a.pb = first ? nullptr : pb;
+  a.npb = npb;
+  a.iters = iters;
   const LoadP<float> ld{z, pold, sc, first, 0.0f};
   launch_f32<M_PA>(c, 1, ld, a);
 }

@@ -792,14 +792,29 @@ static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, d
     HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     float *pold = p0, *pnew = p1;
+    // conduction: the finalizers run inside the sweeps, as in the FP64 Jacobi
+    // solve; the 7-point operator keeps the finalize kernels
+    const bool fused = ctx->op == OP_SPITZER;
+    double *part_b = part + 2 * cap;
     st = pcg_iterate(ctx, sc, maxit - total, [&](int it) {
-      f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
-      launch_finalize_alpha(ctx, part, np3, sc);
-      f32_pass_b(ctx, e, pnew, r, y, iv, z, part, sc);
-      launch_finalize_beta(ctx, part, np1, sc);
+      if (fused) {
+        f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, np1, it);
+        f32_pass_b(ctx, e, pnew, r, y, iv, z, part_b, sc, part, np3);
+      } else {
+        f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
+        launch_finalize_alpha(ctx, part, np3, sc);
+        f32_pass_b(ctx, e, pnew, r, y, iv, z, part, sc);
+        launch_finalize_beta(ctx, part, np1, sc);
+      }
       std::swap(pold, pnew);
     });
     if (st) return st;
+    if (fused && maxit - total > 0 && !h->done) {
+      launch_finalize_check(ctx, part_b, np1, maxit - total, sc);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
     if (h->status == -4) FAIL(STS_BREAKDOWN, "FP32 form: inner PCG breakdown");
     total += h->iters;
     f32_add_to(ctx, x, e);

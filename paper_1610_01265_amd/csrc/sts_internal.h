@@ -173,14 +173,18 @@ void f32_apply(const sts_ctx *c, int ncomp, const double *u, double *Fu);
 void f32_stage(const sts_ctx *c, int last, int ncomp, const float *dkm1, const float *dkm2,
                const float *F0, void *out, const double *u0, double mu, double nu, double mut_dt,
                double g_dt);
+// pb / pa != null: the in-sweep finalizers, as launch_pass_a and
+// launch_pass_b_jacobi_fused
 void f32_pass_a(const sts_ctx *c, double dt, const float *z, const float *pold, float *pnew,
-                float *y, double *part, const PcgScalars *sc, int first);
+                float *y, double *part, const PcgScalars *sc, int first,
+                const double *pb = nullptr, int npb = 0, int iters = 0);
 void f32_residual(const sts_ctx *c, const double *b, const double *x, double dt, double *r,
                   double *part);
 void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, float *r,
                     float *invd, float *e, float *z, double *part);
 void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const float *y,
-                const float *invd, float *z, double *part, const PcgScalars *sc);
+                const float *invd, float *z, double *part, const PcgScalars *sc,
+                const double *pa = nullptr, int npa = 0);
 void f32_add_to(const sts_ctx *c, double *x, const float *e);
 void launch_fill_f32(const sts_ctx *c, float *p, long long n, float v);
 

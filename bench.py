@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--learned-train-seeds", type=int, default=200,
                     help="training pairs (seeds 1..N) for the network before the timed steps")
     ap.add_argument("--learned-epochs", type=int, default=4)
+    ap.add_argument("--pair-workers", type=int, default=8,
+                    help="host processes generating the training fields (1: in this process, "
+                         "as under a profiler)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="before the steps, run a plain device copy of 4 fields (known bytes) "
                          "that calibrates the HBM byte counters")
@@ -122,6 +125,11 @@ def cpu_baseline(w, dt_factor, budget_s=12.0, max_steps=8):
             "kind": "oracle",
             "sample": f"{n} RKL2 super-step(s) (s={s}) of {w['workload'].name} "
                       f"({cells} cells), numpy FP64, one thread, {t:.1f} s"}
+
+
+def progress(msg):
+    """One line on stderr per stage of the run (stdout carries only the result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 class Timer:
@@ -273,6 +281,7 @@ def main():
     held = None
     learned_info = {}
     if "learned" in phases:
+        progress("training the guess network (untimed)")
         # network trained (untimed) on seeds 1..N; the timed steps guess for the
         # workload's own seed (not a training pair) and train on a held pair
         net = sts.Cnn(ctx)
@@ -280,7 +289,7 @@ def main():
         prob = learned.Problem((wl.nr, wl.nth, wl.nph))
         t0 = time.perf_counter()
         pairs = learned.make_pairs(prob, range(1, 1 + args.learned_train_seeds), wl.dt_factor,
-                                   rtol=1e-10)
+                                   rtol=1e-10, workers=args.pair_workers)
         learned.fit_norm(net, pairs)
         hist = learned.train(net, pairs, args.learned_epochs, 1e-3)
         torch.cuda.synchronize()
@@ -378,9 +387,11 @@ def main():
         if rec is not None:
             rec.append((tm, info))
 
+    progress("inputs ready; warm-up steps")
     for _ in range(args.warmup):
         step(None)
     torch.cuda.synchronize()
+    progress("timed steps")
     recs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -389,6 +400,7 @@ def main():
     wall = time.perf_counter() - t0
     march = None
     if args.march_steps > 0:
+        progress("successive-step march")
         march = run_march(torch, sts, ctx, T, (br, bt, bp), w["kappa0"], wl, args.march_steps,
                           stream)
     ph = {}
@@ -475,6 +487,7 @@ def main():
                      "mean_launch_us": t_rk / s * 1e6 if s else None},
     }
     if not args.no_cpu_baseline:
+        progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(w, wl.dt_factor)
     print(json.dumps(out), flush=True)
     if net is not None:

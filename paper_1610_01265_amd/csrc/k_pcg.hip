@@ -316,14 +316,6 @@ void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, c->stream, part, stencil_parts(c), sc);
 }
 
-void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
-                          const double *y, const double *invd, double *z, double *part,
-                          const PcgScalars *sc) {
-  hipLaunchKernelGGL(k_pass_b_jac<false>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell,
-                     x, p, r, y, invd, z, part, cap_of(c), (PcgScalars *)sc,
-                     (const double *)nullptr, 0);
-}
-
 void launch_pass_b_jacobi_fused(const sts_ctx *c, double *x, const double *p, double *r,
                                 const double *y, const double *invd, double *z, double *part,
                                 PcgScalars *sc, const double *pa, int npa) {

@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   using R = typename Loader::value_type;
   if (MODE == M_PA && a.sc->done) return;
   __shared__ R s_u[4][PL];
-  if constexpr (MODE == M_PA && OP == OP_SPITZER) {
+  if constexpr (MODE == M_PA) {
     if (a.pb) {
       // the previous iteration's stopping test and this one's beta, from the
       // fused pass B's partials (identical in every workgroup)

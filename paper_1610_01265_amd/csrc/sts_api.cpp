@@ -792,24 +792,15 @@ static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, d
     HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     float *pold = p0, *pnew = p1;
-    // conduction: the finalizers run inside the sweeps, as in the FP64 Jacobi
-    // solve; the 7-point operator keeps the finalize kernels
-    const bool fused = ctx->op == OP_SPITZER;
+    // the finalizers run inside the sweeps, as in the FP64 Jacobi solve
     double *part_b = part + 2 * cap;
     st = pcg_iterate(ctx, sc, maxit - total, [&](int it) {
-      if (fused) {
-        f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, np1, it);
-        f32_pass_b(ctx, e, pnew, r, y, iv, z, part_b, sc, part, np3);
-      } else {
-        f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
-        launch_finalize_alpha(ctx, part, np3, sc);
-        f32_pass_b(ctx, e, pnew, r, y, iv, z, part, sc);
-        launch_finalize_beta(ctx, part, np1, sc);
-      }
+      f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, np1, it);
+      f32_pass_b(ctx, e, pnew, r, y, iv, z, part_b, sc, part, np3);
       std::swap(pold, pnew);
     });
     if (st) return st;
-    if (fused && maxit - total > 0 && !h->done) {
+    if (maxit - total > 0 && !h->done) {
       launch_finalize_check(ctx, part_b, np1, maxit - total, sc);
       LAUNCHCHK();
       HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
@@ -885,23 +876,18 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   const int np3 = stencil_parts(ctx);
-  // Jacobi on the conduction operator: two launches per iteration.  Pass B
-  // forms alpha from pass A's partials (region 0) and writes its own to
-  // regions 2 and 3; the next pass A evaluates the stopping test and beta from
-  // those, so no kernel sits between the sweeps (-4 to -5 % per solve).
+  // Jacobi: two launches per iteration.  Pass B forms alpha from pass A's
+  // partials (region 0) and writes its own to regions 2 and 3; the next pass A
+  // evaluates the stopping test and beta from those, so no kernel sits
+  // between the sweeps (-4 to -5 % per solve, conduction and viscosity).
   // Block ILU0 keeps the separate finalizers (fused, its latency-bound solve
-  // sweep measured no faster), and so does the 7-point operator (its pass A
-  // would lose a wave per SIMD to the fused prologue).
+  // sweep measured no faster).
   double *part_b = part + 2 * cap;
-  const bool fused = !ilu && ctx->op == OP_SPITZER;
   st = pcg_iterate(ctx, sc, maxit, [&](int it) {
-    if (!fused) {
+    if (ilu) {
       launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
       launch_finalize_alpha(ctx, part, np3, sc);
-      if (ilu)
-        launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
-      else
-        launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, z, part, sc);
+      launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
       launch_finalize_beta(ctx, part, nb_parts, sc);
     } else {
       launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, nb_parts, it);
@@ -910,7 +896,7 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
     std::swap(pold, pnew);
   });
   if (st) return st;
-  if (fused && maxit > 0 && !h->done) {
+  if (!ilu && maxit > 0 && !h->done) {
     // every one of the maxit iterations ran; evaluate the last one's end
     launch_finalize_check(ctx, part_b, nb_parts, maxit, sc);
     LAUNCHCHK();

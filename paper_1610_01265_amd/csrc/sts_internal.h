@@ -213,13 +213,9 @@ void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *p
                    double *pnew, double *y, double *part, const PcgScalars *sc, int first,
                    const double *pb = nullptr, int npb = 0, int iters = 0);
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
-// also stores z = r / A_ii of the updated residual for the next pass A
-void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
-                          const double *y, const double *invd, double *z, double *part,
-                          const PcgScalars *sc);
 void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
 // Jacobi pass B that forms alpha itself from pass A's partials pa (npa), then
-// updates x, r, z and writes its partials (r.z, r.r) to part, part + cap; the
+// updates x, r, z (z = r / A_ii, for the next pass A) and writes its partials (r.z, r.r) to part, part + cap; the
 // end of its iteration is evaluated by the next fused pass A, or, after the
 // last one, by launch_finalize_check.
 void launch_pass_b_jacobi_fused(const sts_ctx *c, double *x, const double *p, double *r,

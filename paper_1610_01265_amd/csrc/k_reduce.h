@@ -42,7 +42,8 @@ __device__ __forceinline__ void wg_sum2(double a, double b, int tid, double *out
 // 256 threads, in a fixed order: each thread issues its (up to) 8 loads of a
 // 2048-entry round at once, then wave shuffles and the four wave totals in
 // a fixed order.  (One round of independent loads instead of a chain of
-// dependent ones; the finalizers sit between every two PCG sweeps.)  tid is
+// dependent ones; these sums sit between every two PCG sweeps, in a finalize
+// kernel or at the start of the next sweep.)  tid is
 // the thread's linear index in a workgroup of 256 (x fastest).
 __device__ __forceinline__ void block_sum_parts(const double *part, int n, long long stride,
                                                 double *s0, double *s1,

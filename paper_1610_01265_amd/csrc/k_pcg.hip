@@ -300,16 +300,16 @@ void launch_init_p_n(const sts_ctx *c, long long n, const double *r, const doubl
                      (const double *)nullptr, p, part, (double *)nullptr);
 }
 
-void launch_finalize_alpha_n(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc) {
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, c->stream, part, nparts, sc);
-}
-
 void launch_pass_b_jacobi_n(const sts_ctx *c, long long n, double *x, const double *p, double *r,
                             const double *y, const double *invd, double *part, int nparts,
-                            const PcgScalars *sc) {
-  hipLaunchKernelGGL(k_pass_b_jac<false>, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y,
-                     invd, (double *)nullptr, part, cap_of(c), (PcgScalars *)sc,
-                     (const double *)nullptr, 0);
+                            const PcgScalars *sc, const double *pa, int npa) {
+  PcgScalars *s = const_cast<PcgScalars *>(sc);
+  if (pa)
+    hipLaunchKernelGGL(k_pass_b_jac<true>, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y,
+                       invd, (double *)nullptr, part, cap_of(c), s, pa, npa);
+  else
+    hipLaunchKernelGGL(k_pass_b_jac<false>, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y,
+                       invd, (double *)nullptr, part, cap_of(c), s, (const double *)nullptr, 0);
 }
 
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars *sc) {

@@ -259,13 +259,23 @@ __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict
   }
 }
 
-// p = z + beta p_old with z = r / diag (beta = 0 on the first iteration)
+// p = z + beta p_old with z = r / diag (beta = 0 on the first iteration).
+// pb != null: beta and the previous iteration's stopping test are formed here
+// from pass B's partials pb (npb per region, regions cap apart), identically
+// in every workgroup (pcg_decide), instead of in a finalize kernel.
 __global__ void __launch_bounds__(RT)
     k_rpa(long long n, const double *__restrict__ r, const double *__restrict__ invd,
-          const double *__restrict__ pold, double *__restrict__ p, const PcgScalars *sc,
-          int first) {
+          const double *__restrict__ pold, double *__restrict__ p, PcgScalars *sc, int first,
+          const double *pb, int npb, long long cap, int iters) {
   if (sc->done) return;
-  const double beta = first ? 0.0 : sc->beta;
+  double beta = 0.0;
+  if (!first) {
+    if (pb) {
+      if (pcg_decide(pb, npb, cap, iters, sc, blockIdx.x == 0, (int)threadIdx.x, &beta)) return;
+    } else {
+      beta = sc->beta;
+    }
+  }
   for (long long e = (long long)blockIdx.x * RT + threadIdx.x; e < n;
        e += (long long)gridDim.x * RT)
     p[e] = r[e] * invd[e] + (first ? 0.0 : beta * pold[e]);
@@ -380,11 +390,11 @@ void launch_res_residual(const sts_ctx *c, const double *b, const double *x, dou
 
 void launch_res_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
                        const double *pold, double *p, double *Phi, double *y, double *part,
-                       const PcgScalars *sc, int first) {
+                       const PcgScalars *sc, int first, const double *pb, int npb, int iters) {
   const RDims d = rdims(c);
   const long long n = d.ne[0] + d.ne[1] + d.ne[2];
-  hipLaunchKernelGGL(k_rpa, dim3(res_parts(c)), dim3(RT), 0, c->stream, n, r, invd, pold, p, sc,
-                     first);
+  hipLaunchKernelGGL(k_rpa, dim3(res_parts(c)), dim3(RT), 0, c->stream, n, r, invd, pold, p,
+                     const_cast<PcgScalars *>(sc), first, pb, npb, (long long)c->red_cap, iters);
   curl_launch<0, RK_FLUX>(c, d, p, Phi);
   RArgs a{};
   a.in = p;

@@ -1127,14 +1127,22 @@ sts_status resistivity_be_pcg_solve(sts_ctx *ctx, const double *E_n, double *E, 
   HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   {
+    // alpha, beta and the stopping test inside the sweeps, as in be_pcg_solve:
+    // pass B's partials go to regions 2 and 3
+    double *part_b = part + 2 * cap;
     const sts_status st = pcg_iterate(ctx, sc, maxit, [&](int it) {
-      launch_res_pass_a(ctx, dt, r, invd, pold, pnew, Phi, y, part, sc, it == 0);
-      launch_finalize_alpha_n(ctx, part, P, sc);
-      launch_pass_b_jacobi_n(ctx, ne, E, pnew, r, y, invd, part, P, sc);
-      launch_finalize_beta(ctx, part, P, sc);
+      launch_res_pass_a(ctx, dt, r, invd, pold, pnew, Phi, y, part, sc, it == 0, part_b, P, it);
+      launch_pass_b_jacobi_n(ctx, ne, E, pnew, r, y, invd, part_b, P, sc, part, P);
       std::swap(pold, pnew);
     });
     if (st) return st;
+    if (maxit > 0 && !h->done) {
+      // every one of the maxit iterations ran; evaluate the last one's end
+      launch_finalize_check(ctx, part_b, P, maxit, sc);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
   }
   if (iters) *iters = h->iters;
   if (relres) *relres = h->bnorm2 > 0 ? std::sqrt(h->rnorm2 / h->bnorm2) : 0.0;

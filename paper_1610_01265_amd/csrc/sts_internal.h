@@ -156,16 +156,19 @@ void launch_res_rhs(const sts_ctx *c, const double *En, double dt, double *x, do
                     double *invd, double *Phi, double *Wf, double *part);
 void launch_res_residual(const sts_ctx *c, const double *b, const double *x, double dt,
                          double *Phi, double *r, double *part);
+// pb != null (and !first): beta and the previous iteration's stopping test
+// from a fused pass B's partials pb (npb), the iteration count being `iters`
 void launch_res_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
                        const double *pold, double *p, double *Phi, double *y, double *part,
-                       const PcgScalars *sc, int first);
+                       const PcgScalars *sc, int first, const double *pb = nullptr,
+                       int npb = 0, int iters = 0);
 // PCG pieces over a vector of n entries (k_pcg.hip)
 void launch_init_p_n(const sts_ctx *c, long long n, const double *r, const double *invd,
                      double *p, double *part, int nparts);
-void launch_finalize_alpha_n(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc);
+// pa != null: alpha from pass A's partials pa (npa) inside the sweep
 void launch_pass_b_jacobi_n(const sts_ctx *c, long long n, double *x, const double *p, double *r,
                             const double *y, const double *invd, double *part, int nparts,
-                            const PcgScalars *sc);
+                            const PcgScalars *sc, const double *pa = nullptr, int npa = 0);
 
 // FP32 form (k_stencil.hip, k_pcg.hip)
 void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1, double mut_dt);

@@ -23,7 +23,10 @@ Modules
   cnn       - FP64 reference of the small 3D CNN used for learned initial guesses
 
 Parity status: every function is pinned by the CPU tests in
-tests/test_oracle_*.py (closed forms, invariants, brute force on tiny grids).
+tests/test_oracle_*.py (closed forms, invariants, brute force on tiny grids);
+among them the block-ILU0 apply by dense solves of (L U) z = r per block
+(ragged and 8^3 blocks) and Adam by its unrolled moment sums over several
+steps with beta1 != beta2.
 The conduction discretisation itself is a reading of the paper's "standard
 scheme" (an exactly symmetric energy form with the same 19-point stencil);
 its agreement with the paper's own scheme is parity unpinned, as no code or

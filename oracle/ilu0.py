@@ -3,22 +3,29 @@
 Sec. 2.3 and Appendix A.  The domain is cut into non-overlapping blocks (the
 paper's per-MPI-rank subdomains; here blocks of b0 x b1 x b2 cells, the last
 block along an axis may be smaller).  Inside each block the matrix A is
-restricted to the block (couplings to other blocks are dropped) and factored
-by the zero-fill IKJ incomplete LU of Appendix A:
+restricted to the block (couplings to other blocks are dropped) and given a
+zero-fill incomplete LU factorisation A ~ L U: L unit lower triangular and U
+upper triangular, both confined to the sparsity pattern P of A, determined by
+the defining equations of zero fill
 
-    for i = 2..N:  for k < i with LU_ik != 0:
-        LU_ik = LU_ik / LU_kk
-        for j > k with LU_ij != 0:  LU_ij = LU_ij - LU_ik LU_kj
+    (L U)_ij = A_ij   for every (i, j) in P.
 
-and applied by the forward / backward substitution of Appendix A.
+Taking the rows in order, each equation has exactly one unknown:
+    j <  i:  L_ij = (A_ij - sum_{m < j} L_im U_mj) / U_jj
+    j >= i:  U_ij =  A_ij - sum_{m < i} L_im U_mj
+(sums over the m with (i, m) and (m, j) in P, taken in ascending m).  The
+preconditioner applies z = U^-1 (L^-1 r) per block, here by sparse triangular
+solves of the block-diagonal L and U (a library primitive).
 
 Readings:
-  * "LU_ij != 0" is the structural pattern of A: the 19-point stencil
-    restricted to the block, including entries that happen to be numerically
-    zero (e.g. next to a boundary); an update LU_ij -= LU_ik LU_kj is applied
-    when (i, j) and (k, j) are both in that pattern.
+  * P is the structural pattern of A: the 19-point stencil restricted to the
+    block, including entries that happen to be numerically zero (e.g. next
+    to a boundary).
   * rows are ordered lexicographically inside the block, axis 0 (r) slowest
     and axis 2 (phi) fastest, i.e. in memory order.  ILU0 depends on this.
+  * the forward substitution of Appendix A subtracts the strictly lower
+    entries only (its printed loop bound includes the diagonal; L has a unit
+    diagonal, which the substitution does not subtract).
   * the periodic phi coupling is a boundary condition (MAS applies BCs
     matrix-free, Sec. 4.2), so it is never part of a block's matrix, even
     for a block that spans the whole phi range.
@@ -27,6 +34,8 @@ With 1x1x1 blocks every block matrix is its diagonal and PC2 equals PC1.
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
+from scipy.sparse.linalg import spsolve_triangular
 
 from .operator import OFFSETS
 
@@ -74,66 +83,77 @@ def _gather_block_values(F, origins, bs):
     return F[..., i0, i1, i2], (i0, i1, i2)
 
 
+def _factor_group(A, pat):
+    """Zero-fill ILU of every block of one shape at once.  A[nb, nrows, 19]
+    holds the block matrices in stencil slots; returns LU of the same layout
+    (strictly lower slots: L, the rest: U; slot 0 is the diagonal)."""
+    LU = np.zeros_like(A)
+    for i, row in enumerate(pat):
+        cols = sorted(row)
+        for j in cols:
+            s = row[j]
+            acc = A[:, i, s].copy()
+            for m in cols:
+                if m >= min(i, j):
+                    break
+                t = pat[m].get(j)
+                if t is not None:
+                    acc -= LU[:, i, row[m]] * LU[:, m, t]
+            LU[:, i, s] = acc / LU[:, j, 0] if j < i else acc
+    return LU
+
+
 def factor(A19: np.ndarray, block) -> dict:
     """Block ILU0 factors.  Returns, per block shape, LU[nblocks, nrows, 19]
-    (values of the combined LU matrix in stencil slots) and the pattern."""
+    (values of L and U in stencil slots), the pattern, and the block-diagonal
+    sparse L and U over all blocks of that shape."""
     shape = A19.shape[1:]
     groups = _shape_groups(shape, tuple(block))
     out = {"shape": shape, "groups": []}
     for bs, origins in groups.items():
         vals, idx = _gather_block_values(A19, origins, bs)  # [19, nb, nrows]
-        LU = np.ascontiguousarray(np.moveaxis(vals, 0, -1))  # [nb, nrows, 19]
+        A = np.ascontiguousarray(np.moveaxis(vals, 0, -1))  # [nb, nrows, 19]
         pat = _pattern(bs)
-        # zero entries outside the block pattern (cross-block couplings dropped)
-        for l, d in enumerate(pat):
-            keep = np.zeros(19, dtype=bool)
-            keep[list(d.values())] = True
-            LU[:, l, ~keep] = 0.0
-        n = len(pat)
-        for i in range(1, n):
-            row = pat[i]
-            cols = sorted(row)
-            for k in cols:
-                if k >= i:
-                    break
-                sik = row[k]
-                LU[:, i, sik] = LU[:, i, sik] / LU[:, k, 0]
-                rowk = pat[k]
-                for j in cols:
-                    if j <= k:
-                        continue
-                    if j in rowk:
-                        LU[:, i, row[j]] -= LU[:, i, sik] * LU[:, k, rowk[j]]
+        LU = _factor_group(A, pat)
         if np.any(~(LU[:, :, 0] > 0)):
             raise FloatingPointError("ILU0 breakdown: non-positive pivot")
-        out["groups"].append(dict(bs=bs, origins=origins, LU=LU, pattern=pat, idx=idx))
+        L, U = _sparse_factors(LU, pat)
+        out["groups"].append(dict(bs=bs, origins=origins, LU=LU, pattern=pat, idx=idx,
+                                  L=L, U=U))
     return out
 
 
+def _sparse_factors(LU, pat):
+    """Block-diagonal CSR matrices of L (unit diagonal stored) and U; block b
+    occupies rows and columns b*n .. b*n + n - 1."""
+    nb, n = LU.shape[0], len(pat)
+    base = (np.arange(nb) * n)[:, None]
+    lr, lc, lv, ur, uc, uv = [], [], [], [], [], []
+    for i, row in enumerate(pat):
+        for j, s in row.items():
+            if j < i:
+                lr.append(base[:, 0] + i), lc.append(base[:, 0] + j), lv.append(LU[:, i, s])
+            else:
+                ur.append(base[:, 0] + i), uc.append(base[:, 0] + j), uv.append(LU[:, i, s])
+        lr.append(base[:, 0] + i), lc.append(base[:, 0] + i), lv.append(np.ones(nb))
+    N = nb * n
+    L = sp.csr_matrix((np.concatenate(lv), (np.concatenate(lr), np.concatenate(lc))),
+                      shape=(N, N))
+    U = sp.csr_matrix((np.concatenate(uv), (np.concatenate(ur), np.concatenate(uc))),
+                      shape=(N, N))
+    return L, U
+
+
 def apply(fac: dict, r: np.ndarray) -> np.ndarray:
-    """z = (LU)^-1 r per block by the forward / backward substitution of
-    Appendix A (unit lower triangle, then the upper triangle with its
-    diagonal)."""
+    """z = U^-1 (L^-1 r) on every block (Appendix A: forward substitution with
+    the unit lower triangle, then backward substitution with the upper one)."""
     z = np.zeros(fac["shape"])
     for grp in fac["groups"]:
-        LU, pat, idx = grp["LU"], grp["pattern"], grp["idx"]
-        rb = r[idx[0], idx[1], idx[2]]  # [nb, nrows]
-        n = len(pat)
-        zs = np.zeros_like(rb)
-        for i in range(n):
-            acc = rb[:, i].copy()
-            for j, s in pat[i].items():
-                if j < i:
-                    acc -= LU[:, i, s] * zs[:, j]
-            zs[:, i] = acc
-        zz = np.zeros_like(rb)
-        for i in range(n - 1, -1, -1):
-            acc = zs[:, i].copy()
-            for j, s in pat[i].items():
-                if j > i:
-                    acc -= LU[:, i, s] * zz[:, j]
-            zz[:, i] = acc / LU[:, i, 0]
-        z[idx[0], idx[1], idx[2]] = zz
+        idx = grp["idx"]
+        rb = r[idx[0], idx[1], idx[2]].ravel()  # block-major, local lexicographic
+        y = spsolve_triangular(grp["L"], rb, lower=True, unit_diagonal=True)
+        zb = spsolve_triangular(grp["U"], y, lower=False)
+        z[idx[0], idx[1], idx[2]] = zb.reshape(idx[0].shape)
     return z
 
 

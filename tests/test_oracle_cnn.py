@@ -112,3 +112,41 @@ def test_adam_moves_against_gradient():
     cnn.adam_step(params, g, st, lr=1e-2)
     for (W, _), W0 in zip(params, before):
         assert np.allclose(W - W0, -1e-2, rtol=1e-6)
+
+
+def test_adam_matches_closed_form_sums_over_steps():
+    """Adam after t steps with a varying gradient, against the unrolled moment
+    sums m_t = (1-b1) sum_s b1^(t-s) g_s, v_t = (1-b2) sum_s b2^(t-s) g_s^2 and
+    the bias corrections 1 - b^t of that t.  b1 != b2 (0.5 and 0.75), so
+    swapping them, dropping a correction or using the wrong t fails."""
+    b1, b2, lr, eps = 0.5, 0.75, 1e-2, 1e-8
+    rng = np.random.default_rng(7)
+    params = cnn.init_params(channels=2, layers=2, seed=1)
+    st = cnn.adam_init(params)
+    p0 = [[W.copy(), b.copy()] for W, b in params]
+    gs = []
+    for t in range(1, 6):
+        g = [[rng.standard_normal(W.shape), rng.standard_normal(b.shape)] for W, b in params]
+        gs.append(g)
+        st = cnn.adam_step(params, g, st, lr, beta1=b1, beta2=b2, eps=eps)
+        assert st[2] == t
+        # replay the parameter trajectory in closed form
+        for l in range(len(params)):
+            for q in range(2):
+                x = p0[l][q].copy()
+                for tt in range(1, t + 1):
+                    m = (1 - b1) * sum(b1 ** (tt - s) * gs[s - 1][l][q] for s in range(1, tt + 1))
+                    v = (1 - b2) * sum(b2 ** (tt - s) * gs[s - 1][l][q] ** 2
+                                       for s in range(1, tt + 1))
+                    x = x - lr * (m / (1 - b1 ** tt)) / (np.sqrt(v / (1 - b2 ** tt)) + eps)
+                assert np.max(np.abs(params[l][q] - x)) <= 1e-13
+    # a constant gradient g gives steps of -lr g / (|g| + eps) at every t
+    params = cnn.init_params(channels=2, layers=2, seed=2)
+    st = cnn.adam_init(params)
+    g = [[np.full_like(W, -0.3), np.full_like(b, 2.0)] for W, b in params]
+    for _ in range(4):
+        before = [[W.copy(), b.copy()] for W, b in params]
+        st = cnn.adam_step(params, g, st, lr, beta1=b1, beta2=b2, eps=eps)
+        for (W, b), (W0, bb0) in zip(params, before):
+            assert np.allclose(W - W0, lr * 0.3 / (0.3 + eps), rtol=1e-12)
+            assert np.allclose(b - bb0, -lr * 2.0 / (2.0 + eps), rtol=1e-12)

@@ -69,14 +69,16 @@ def test_true_residual_meets_tolerance():
         assert res.converged and true <= 2e-9
 
 
-def test_ilu0_unit_blocks_equal_jacobi_exactly():
+def test_ilu0_unit_blocks_equal_jacobi():
     """Sec. 2.3: with one grid point per subdomain PC2 is PC1."""
     op, T = shell_op((4, 6, 8))
     A19, b = O.be_system(op, T, 60 * O.gershgorin_dt_euler(op))
     fac = ilu0.factor(A19, (1, 1, 1))
     r = np.random.default_rng(0).standard_normal(T.shape)
     z = ilu0.apply(fac, r)
-    assert np.array_equal(z, r / A19[0])
+    # the triangular solver divides by the pivot up to its own rounding (1 ulp)
+    jac = r / A19[0]
+    assert np.max(np.abs(z - jac) / np.abs(jac)) <= 2.3e-16
 
 
 def test_ilu0_reproduces_A_on_pattern():
@@ -143,3 +145,53 @@ def test_workload_shell32_solvers_agree():
     ri = pcg.be_pcg(op, w["T"], dt, "ilu0", rtol=1e-9)
     assert rj.converged and ri.converged and ri.iters < rj.iters
     assert np.max(np.abs(rj.x - ri.x)) <= 1e-6 * np.max(np.abs(rj.x))
+
+
+@pytest.mark.parametrize("shape,block", [((4, 6, 8), (3, 4, 5)), ((8, 16, 16), (8, 8, 8)),
+                                         ((5, 7, 9), (2, 3, 4))])
+def test_ilu0_apply_equals_dense_solve_per_block(shape, block):
+    """z = (L U)^-1 r on every block, L and U taken densely from the factor and
+    solved by a dense LU of their product: a substitution that used the wrong
+    entries (e.g. r_j instead of z_j, or the diagonal in the forward sweep)
+    fails here, including on ragged blocks."""
+    op, T = shell_op(shape)
+    A19, _ = O.be_system(op, T, 60 * O.gershgorin_dt_euler(op))
+    fac = ilu0.factor(A19, block)
+    r = np.random.default_rng(3).standard_normal(T.shape)
+    z = ilu0.apply(fac, r)
+    nblocks = 0
+    for gi, grp in enumerate(fac["groups"]):
+        idx = grp["idx"]
+        for bi in range(len(grp["origins"])):
+            L, U = ilu0.lower_upper_dense(fac, gi, bi)
+            rb = r[idx[0][bi], idx[1][bi], idx[2][bi]]
+            zd = np.linalg.solve(L @ U, rb)
+            zb = z[idx[0][bi], idx[1][bi], idx[2][bi]]
+            assert np.max(np.abs(zb - zd)) <= 1e-13 * np.max(np.abs(zd))
+            nblocks += 1
+    assert nblocks == np.prod([-(-n // b) for n, b in zip(shape, block)])
+
+
+def test_ilu0_whole_block_is_dense_zero_fill_lu():
+    """One block covering a tiny grid: the factor equals a dense textbook
+    zero-fill ILU (IKJ elimination on a dense copy, fill outside the pattern
+    discarded) of the dense block matrix."""
+    shape = (3, 4, 5)
+    op, T = shell_op(shape)
+    A19, _ = O.be_system(op, T, 60 * O.gershgorin_dt_euler(op))
+    fac = ilu0.factor(A19, shape)
+    Ab, pat = ilu0.block_dense_A(A19, shape, (0, 0, 0))
+    n = Ab.shape[0]
+    mask = Ab != 0
+    for i, d in enumerate(pat):
+        mask[i, list(d.keys())] = True
+    W = Ab.copy()
+    for i in range(1, n):
+        for k in range(i):
+            if not mask[i, k]:
+                continue
+            W[i, k] /= W[k, k]
+            W[i, k + 1:] -= W[i, k] * W[k, k + 1:] * mask[i, k + 1:]
+    L, U = ilu0.lower_upper_dense(fac, 0, 0)
+    assert np.max(np.abs(np.tril(W, -1) - (L - np.eye(n)))) <= 1e-13 * np.abs(Ab).max()
+    assert np.max(np.abs(np.triu(W) - U)) <= 1e-13 * np.abs(Ab).max()

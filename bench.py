@@ -10,8 +10,10 @@ One step = one pass of the whole path over the synthetic shell input:
     (mixed-precision refinement to the same FP64 residual);
   * artificial viscosity on a 3-component velocity field: RKL2 step of all
     three components and one Jacobi-PCG BE solve per component;
-  * the learned initial guess: cnn_guess (network + residual fallback),
-    Jacobi-PCG from that guess, and one training step of the network;
+  * the learned initial guess on its own grid (128 x 128 x 256, dt = 200
+    dt_Euler): coefficient set-up, cnn_guess (network + residual fallback),
+    Jacobi-PCG from that guess and from the previous-step guess, and one
+    training step of the network;
   * the super-step variants of Sec. 6 on the temperature: RKL2 in 10
     sub-cycles, explicit Euler over a quarter step then RKL2, and RKL1 with
     one extra stage;
@@ -23,12 +25,15 @@ Inputs are resident in HBM before the timed region.  After the timed steps,
 a march of 10 successive steps per method (RKL2, Jacobi-PCG, block-ILU0-PCG)
 re-freezes kappa from each method's evolving state at every step and reports
 per-step times, stage counts and iteration counts ("successive_steps").  Each phase is bracketed
-by HIP events on the library's stream.  `value` is the RKL2 throughput in
-cell-stage updates per second; the BE solve times are reported beside it.
+by HIP events on the library's stream; phase times are medians over the timed
+steps (means beside them).  `value` is the RKL2 throughput in cell-stage
+updates per second; the BE solve times are reported beside it.  The host
+fields of the learned guess's training set are generated in a process pool
+before this process touches the GPU.
 
 The roofline entry is for the RKL2 stage kernel (the fused stencil + stage
 update): algorithmic bytes per launch (72 B/cell for stage 1, 88 B/cell for
-stages 2..s) over the mean launch duration (RKL2 phase time / s).  `traffic`
+stages 2..s) over the mean launch duration (median RKL2 phase time / s).  `traffic`
 is the copy-calibrated HBM byte count per launch from the committed counter
 summary of the same kernel, or null when the kernel's sources have changed
 since those counters were taken.
@@ -48,16 +53,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_rkl2_stage_shell128_pmc.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_rkl2_stage_shell256_pmc.txt")
+LEARNED_SHAPE = (128, 128, 256)  # grid of the learned-guess workload
+LEARNED_RATIO = 200.0            # its dt / dt_Euler
 STAGE_SOURCES = ["k_stencil.hip", "k_row.h", "k_common.h", "sts_internal.h"]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="shell128")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="shell256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases",
                     default="rkl2,jacobi,ilu0,fp32,visc,learned,variants,nonlinear,resist",
@@ -69,8 +76,8 @@ def parse():
                     help="training pairs (seeds 1..N) for the network before the timed steps")
     ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--pair-workers", type=int, default=8,
-                    help="host processes generating the training fields (1: in this process, "
-                         "as under a profiler)")
+                    help="host processes generating the training fields before the GPU is "
+                         "initialised (1: in this process)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="before the steps, run a plain device copy of 4 fields (known bytes) "
                          "that calibrates the HBM byte counters")
@@ -104,27 +111,38 @@ def read_traffic(ncell):
         return None
 
 
-def cpu_baseline(w, dt_factor, budget_s=12.0, max_steps=8):
+def cpu_baseline(w, dt_factor, budget_s=12.0, max_steps=8, max_cells=1 << 22):
     """The oracle as it stands, timed on this host: RKL2 super-steps of the
-    same workload, repeated until about budget_s seconds (the bounded sample)."""
+    same workload, repeated until about budget_s seconds (the bounded sample).
+    Grids above max_cells are sampled by their innermost r-planes (the slab
+    keeps the Dirichlet inner boundary; its outer cut is zero-flux), so that
+    one super-step stays within a few seconds."""
     from oracle import operator as O
     from oracle import rkl2 as orkl2
-    D = O.spitzer_tensor(w["T"], w["kappa0"], w["br"], w["bt"], w["bp"])
-    op = O.assemble("spherical", w["rf"], w["thf"], w["phf"], D, O.SHELL_BC, u_lo=w["T_inner"])
+    T = w["T"]
+    n12 = T.shape[1] * T.shape[2]
+    nr = min(T.shape[0], max(1, max_cells // n12))
+    sl = slice(0, nr)
+    D = O.spitzer_tensor(T[sl], w["kappa0"], w["br"][sl], w["bt"][sl], w["bp"][sl])
+    op = O.assemble("spherical", w["rf"][:nr + 1], w["thf"], w["phf"], D, O.SHELL_BC,
+                    u_lo=w["T_inner"])
     dte = O.gershgorin_dt_euler(op)
     s = orkl2.stage_count(dt_factor)
+    Ts = np.ascontiguousarray(T[sl])
     t = 0.0
     n = 0
     while n < max_steps and (n == 0 or t < budget_s):
         t0 = time.perf_counter()
-        orkl2.rkl2_step(lambda v: O.apply_F(op, v), w["T"], dt_factor * dte, s)
+        orkl2.rkl2_step(lambda v: O.apply_F(op, v), Ts, dt_factor * dte, s)
         t += time.perf_counter() - t0
         n += 1
-    cells = w["T"].size
+    cells = Ts.size
+    part = ("" if nr == T.shape[0] else
+            f"the {nr} innermost r-planes ({nr}x{T.shape[1]}x{T.shape[2]} = {cells} cells) of ")
     return {"value": n * cells * s / t, "unit": "cell-stage updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{n} RKL2 super-step(s) (s={s}) of {w['workload'].name} "
-                      f"({cells} cells), numpy FP64, one thread, {t:.1f} s"}
+            "sample": f"{n} RKL2 super-step(s) (s={s}) of {part}{w['workload'].name} "
+                      f"({T.size} cells), numpy FP64, one thread, {t:.1f} s"}
 
 
 def progress(msg):
@@ -233,6 +251,12 @@ def resist_entry(ph, info, ctxr):
 RES_BYTES_PER_EDGE = 128
 
 
+def median(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return 0.5 * (xs[(n - 1) // 2] + xs[n // 2]) if n else 0.0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -246,6 +270,15 @@ def main():
     from workloads import WORKLOADS, edge_potential, flatten, he_normal, make_workload
 
     wl = WORKLOADS[args.workload]
+    phases = args.phases.split(",")
+    # host fields of the learned guess (training seeds 1..N and the evaluated
+    # seed 0), generated before anything here touches the GPU
+    lfields = None
+    if "learned" in phases:
+        progress("generating the learned guess's host fields")
+        lfields = learned.host_fields(LEARNED_SHAPE, range(0, 1 + args.learned_train_seeds),
+                                      args.pair_workers)
+    progress("generating the workload's host fields")
     w = make_workload(wl, with_velocity=True)
     torch.cuda.set_device(0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
@@ -254,7 +287,6 @@ def main():
     T32, br32, bt32, bp32 = T.to(f32), br.to(f32), bt.to(f32), bp.to(f32)
     v0 = dev(np.stack(w["v"]))
     nu = w["nu"]
-    phases = args.phases.split(",")
 
     def shell_ctx(u_lo):
         c = sts.Context(sts.SPHERICAL, w["rf"], w["thf"], w["phf"], sts.SHELL_BC)
@@ -279,24 +311,28 @@ def main():
 
     net = None
     held = None
+    lprob = None
     learned_info = {}
     if "learned" in phases:
         progress("training the guess network (untimed)")
-        # network trained (untimed) on seeds 1..N; the timed steps guess for the
-        # workload's own seed (not a training pair) and train on a held pair
-        net = sts.Cnn(ctx)
+        # network trained (untimed) on seeds 1..N of its own grid; the timed
+        # steps guess for seed 0 (not a training pair) and train on a held pair
+        lprob = learned.Problem(LEARNED_SHAPE)
+        net = sts.Cnn(lprob.ctx)
         net.set_weights(flatten(he_normal(4, 16, 0)))
-        prob = learned.Problem((wl.nr, wl.nth, wl.nph))
         t0 = time.perf_counter()
-        pairs = learned.make_pairs(prob, range(1, 1 + args.learned_train_seeds), wl.dt_factor,
-                                   rtol=1e-10, workers=args.pair_workers)
+        pairs = learned.make_pairs(lprob, lfields[1:], LEARNED_RATIO, rtol=1e-10)
         learned.fit_norm(net, pairs)
         hist = learned.train(net, pairs, args.learned_epochs, 1e-3)
         torch.cuda.synchronize()
-        learned_info = {"train_pairs": len(pairs), "epochs": args.learned_epochs,
+        learned_info = {"grid": list(LEARNED_SHAPE), "dt_over_dt_euler": LEARNED_RATIO,
+                        "train_pairs": len(pairs), "epochs": args.learned_epochs,
                         "loss_per_epoch": hist, "pretrain_s": time.perf_counter() - t0}
         held = pairs[0]
         del pairs
+        TL = dev(lfields[0][1])
+        xl = torch.empty_like(TL)
+        lfields = None
 
     if args.copy_calib:
         src = torch.empty(4 * ncell, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -352,13 +388,23 @@ def main():
                 it, _, _ = ctxv.be_pcg_solve(v0[m], xv, dtv, pc=sts.PC_JACOBI, rtol=wl.rtol)
                 its.append(it)
             info["it_visc"] = its
+        tm.mark("learned_setup")
+        if "learned" in phases:
+            dtl = LEARNED_RATIO * lprob.set_temperature(TL)
         tm.mark("learned_guess")
         if "learned" in phases:
-            _, used, rel = net.guess(T, dt, x)
+            _, used, rel = net.guess(TL, dtl, xl)
             info["guess_used_net"], info["guess_relres"] = used, rel
         tm.mark("learned_jacobi")
         if "learned" in phases:
-            info["it_learned"], _, _ = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_JACOBI, rtol=wl.rtol)
+            info["it_learned"], _, _ = lprob.ctx.be_pcg_solve(TL, xl, dtl, pc=sts.PC_JACOBI,
+                                                              rtol=wl.rtol)
+        tm.mark("learned_prev_jacobi")
+        if "learned" in phases:
+            xl.copy_(TL)
+            info["it_learned_prev"], _, _ = lprob.ctx.be_pcg_solve(TL, xl, dtl,
+                                                                   pc=sts.PC_JACOBI,
+                                                                   rtol=wl.rtol)
         tm.mark("learned_train")
         if "learned" in phases:
             net.train_step(held.F, held.dt, held.T, held.x_star, 1e-4, want_loss=False)
@@ -387,26 +433,29 @@ def main():
         if rec is not None:
             rec.append((tm, info))
 
-    progress("inputs ready; warm-up steps")
+    progress(f"inputs ready; {args.warmup} warm-up steps")
     for _ in range(args.warmup):
         step(None)
     torch.cuda.synchronize()
-    progress("timed steps")
+    progress(f"{args.steps} timed steps")
     recs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(recs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    progress("timed steps done")
     march = None
     if args.march_steps > 0:
         progress("successive-step march")
         march = run_march(torch, sts, ctx, T, (br, bt, bp), w["kappa0"], wl, args.march_steps,
                           stream)
-    ph = {}
+    per = {}
     for tm, _ in recs:
         for k, val in tm.intervals().items():
-            ph[k] = ph.get(k, 0.0) + val / len(recs)
+            per.setdefault(k, []).append(val)
+    ph = {k: median(vals) for k, vals in per.items()}
+    ph_mean = {k: sum(vals) / len(vals) for k, vals in per.items()}
     info = recs[-1][1]
     sec = {k: val / 1e3 for k, val in ph.items()}
     s = info.get("s", 0)
@@ -421,12 +470,12 @@ def main():
     def ratio(a, b):
         return a / b if (a > 0 and b > 0) else None
 
-    def pcg_hbm(iters, bpc, seconds):
+    def pcg_hbm(iters, bpc, seconds, cells=ncell):
         """Algorithmic bytes of the iterations over the whole solve time
         (set-up included, so a lower bound on the sweeps' own rate)."""
         if not iters or seconds <= 0:
             return None
-        gbs = iters * bpc * ncell / seconds / 1e9
+        gbs = iters * bpc * cells / seconds / 1e9
         return {"alg_bytes_per_cell_iteration": bpc, "achieved_GBs": gbs,
                 "frac_hbm": gbs / HBM_PEAK_GBS}
 
@@ -446,17 +495,23 @@ def main():
         "config": {"workload": f"{wl.name}: spherical shell {wl.nr}x{wl.nth}x{wl.nph} "
                                f"({ncell} cells), Spitzer conduction, tilted dipole b, "
                                f"dt = {wl.dt_factor:g} dt_Euler, rtol {wl.rtol:g}; viscosity "
-                               f"on 3 velocity components; learned guess (4-layer CNN)",
+                               f"on 3 velocity components; learned guess (4-layer CNN) on "
+                               f"{'x'.join(map(str, LEARNED_SHAPE))}",
                    "rkl2_stages": s, "ilu_block": list(wl.block)},
+        "timing": "phase times: median over the timed steps (HIP events on the library's "
+                  "stream), after the warm-up steps",
         "phase_ms": ph,
+        "phase_ms_mean": ph_mean,
         "be_pcg_s_per_solve": {"jacobi": t_jac, "block_ilu0_8x8x8": sec["ilu0"],
                                "fp32_form_jacobi": sec["fp32_jacobi"],
-                               "learned_guess_jacobi": t_learn,
-                               "viscosity_jacobi_per_component": sec["visc_jacobi"] / 3},
+                               "viscosity_jacobi_per_component": sec["visc_jacobi"] / 3,
+                               "learned_grid_jacobi_from_previous": sec["learned_prev_jacobi"],
+                               "learned_grid_jacobi_from_guess_incl_guess": t_learn},
         "be_pcg_iters": {"jacobi": info.get("it_jac"), "block_ilu0_8x8x8": info.get("it_ilu"),
                          "fp32_form_jacobi_inner": info.get("it_jac32"),
-                         "learned_guess_jacobi": info.get("it_learned"),
-                         "viscosity_jacobi": info.get("it_visc")},
+                         "viscosity_jacobi": info.get("it_visc"),
+                         "learned_grid_jacobi_from_previous": info.get("it_learned_prev"),
+                         "learned_grid_jacobi_from_guess": info.get("it_learned")},
         "be_pcg_hbm": {"jacobi": pcg_hbm(info.get("it_jac"), 144, t_jac),
                        "block_ilu0_8x8x8": pcg_hbm(info.get("it_ilu"), 216, sec["ilu0"]),
                        "viscosity_jacobi": pcg_hbm(sum(info.get("it_visc") or []), 96,
@@ -464,9 +519,9 @@ def main():
         "speedup_vs_fp64_jacobi_pcg": {
             "block_ilu0_8x8x8": ratio(t_jac, sec["ilu0"]),
             "fp32_form_jacobi": ratio(t_jac, sec["fp32_jacobi"]),
-            "learned_guess_jacobi": ratio(t_jac, t_learn),
             "rkl2_step": ratio(t_jac, t_rk),
-            "fp32_form_rkl2_step": ratio(t_jac, sec["fp32_rkl2"])},
+            "fp32_form_rkl2_step": ratio(t_jac, sec["fp32_rkl2"]),
+            "learned_guess_jacobi_on_its_grid": ratio(sec["learned_prev_jacobi"], t_learn)},
         "successive_steps": march,
         "super_step_variants": {
             "rkl2_10_subcycles": {"ms": ph.get("var_subcycle10"),
@@ -492,7 +547,8 @@ def main():
     print(json.dumps(out), flush=True)
     if net is not None:
         net.close()
-    for c in (ctx, ctx32, ctxv) + ((ctxr,) if ctxr is not None else ()):
+    for c in (ctx, ctx32, ctxv) + ((ctxr,) if ctxr is not None else ()) + (
+            (lprob.ctx,) if lprob is not None else ()):
         c.close()
 
 

@@ -320,7 +320,25 @@ sts_status cnn_weight_grad(sts_cnn *net, int layer, const void *act16, const voi
 sts_status cnn_forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
                        double *x0);
 
-/* cnn_train_step - one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, rate lr)
+/* cnn_set_adam - the constants of the Adam optimiser (Kingma & Ba, 2015)
+ * used by cnn_train_step and cnn_adam_step: moment decay rates beta1,
+ * beta2 in [0, 1) and eps > 0 (defaults 0.9, 0.999, 1e-8; held as FP32).
+ * Takes effect at the next step; the moments are kept.  */
+sts_status cnn_set_adam(sts_cnn *net, double beta1, double beta2, double eps);
+
+/* cnn_adam_step - one Adam step of the FP32 master parameters with the
+ * caller's gradient grad (a DEVICE FP32 array of layers * 6928 values, per
+ * layer in the padded layout cnn_weight_grad writes; entries of padding,
+ * which has no parameter, are ignored), rate lr > 0.  With t the number of
+ * steps taken since cnn_set_weights, including this one:
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   p = p - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * in FP32, then the bf16 copies of the weights are refreshed.  For a caller
+ * that forms the gradient itself (e.g. summed over several samples or
+ * devices).  Does not synchronise.  */
+sts_status cnn_adam_step(sts_cnn *net, const float *grad, float lr);
+
+/* cnn_train_step - one Adam step (constants of cnn_set_adam, rate lr)
  * on the loss mean_cells (d - (x_star - T_prev) / delta_scale)^2, with
  * gradients by back-propagation through the same kernels.  *loss (may be
  * NULL; then the call does not synchronise) receives the loss before the

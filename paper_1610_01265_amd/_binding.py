@@ -77,6 +77,8 @@ def load():
         "cnn_weight_grad": (I, [P, I, P, P, P]),
         "cnn_forward": (I, [P, P, D, P, P]),
         "cnn_train_step": (I, [P, P, D, P, P, ctypes.c_float, PD]),
+        "cnn_set_adam": (I, [P, D, D, D]),
+        "cnn_adam_step": (I, [P, P, ctypes.c_float]),
         "cnn_guess": (I, [P, P, D, P, PI, PD]),
     }
     for name, (res, args) in sig.items():
@@ -96,7 +98,8 @@ def exported_symbols():
             "resistivity_be_pcg_solve", "be_pcg_solve",
             "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
             "cnn_get_weights", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
-            "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_guess"]
+            "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_set_adam", "cnn_adam_step",
+            "cnn_guess"]
 
 
 def _ptr(t: torch.Tensor | None, ncell: int, name: str, ncomp: int | None = 1,
@@ -429,6 +432,16 @@ class Cnn:
                                            float(lr), ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
+    def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._chk(self._lib.cnn_set_adam(self._h, float(beta1), float(beta2), float(eps)))
+
+    def adam_step(self, grad, lr):
+        """One Adam step with a device FP32 gradient of layers * 6928 values."""
+        self.ctx._sync_stream()
+        n = self.layers * CNN_PADDED_PARAMS
+        self._chk(self._lib.cnn_adam_step(self._h, _ptr(grad, n, "grad", 1, dtype=torch.float32),
+                                          float(lr)))
+
     def guess(self, T_prev, dt, x0=None):
         """Returns (x0, used_net, (relres_net, relres_prev))."""
         self.ctx._sync_stream()
@@ -551,6 +564,14 @@ def cnn_forward(net: Cnn, F_prev, dt, T_prev, x0=None):
 
 def cnn_train_step(net: Cnn, F_prev, dt, T_prev, x_star, lr, want_loss=True):
     return net.train_step(F_prev, dt, T_prev, x_star, lr, want_loss)
+
+
+def cnn_set_adam(net: Cnn, beta1=0.9, beta2=0.999, eps=1e-8):
+    return net.set_adam(beta1, beta2, eps)
+
+
+def cnn_adam_step(net: Cnn, grad, lr):
+    return net.adam_step(grad, lr)
 
 
 def cnn_guess(net: Cnn, T_prev, dt, x0=None):

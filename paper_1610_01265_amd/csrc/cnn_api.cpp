@@ -77,6 +77,15 @@ void forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev
 
 bool finite_nonzero(double x) { return std::isfinite(x) && x != 0.0; }
 
+// one Adam step of the master parameters with gradient G (padded layout),
+// then the bf16 fragments of the updated weights
+void adam(sts_cnn *net, const float *G, float lr) {
+  net->step += 1;
+  launch_cnn_adam(net->launch(), net->layers * kCnnPPerLayer, net->d_P, net->d_M, net->d_V, G,
+                  net->d_mask, lr, net->step, net->adam_b1, net->adam_b2, net->adam_eps);
+  refresh_frags(net);
+}
+
 }  // namespace
 
 extern "C" {
@@ -329,10 +338,7 @@ sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const d
       q = 1 - q;
     }
   }
-  net->step += 1;
-  launch_cnn_adam(L, net->layers * kCnnPPerLayer, net->d_P, net->d_M, net->d_V, net->d_G,
-                  net->d_mask, lr, net->step);
-  refresh_frags(net);
+  adam(net, net->d_G, lr);
   NLAUNCHCHK();
   if (loss) {
     double h;
@@ -340,6 +346,26 @@ sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const d
     NHIPCHK(hipStreamSynchronize(net->ctx->stream));
     *loss = h / (double)net->ncell;
   }
+  return STS_OK;
+}
+
+sts_status cnn_set_adam(sts_cnn *net, double beta1, double beta2, double eps) {
+  if (!net) return STS_EINVAL;
+  if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+    NFAIL(STS_EINVAL, "cnn_set_adam: beta1 and beta2 must lie in [0, 1)");
+  if (!(eps > 0.0) || !std::isfinite(eps)) NFAIL(STS_EINVAL, "cnn_set_adam: eps must be > 0");
+  net->adam_b1 = (float)beta1;
+  net->adam_b2 = (float)beta2;
+  net->adam_eps = (float)eps;
+  return STS_OK;
+}
+
+sts_status cnn_adam_step(sts_cnn *net, const float *grad, float lr) {
+  if (!net) return STS_EINVAL;
+  if (!grad) NFAIL(STS_EINVAL, "cnn_adam_step: null gradient");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) NFAIL(STS_EINVAL, "cnn_adam_step: lr must be > 0");
+  adam(net, grad, lr);
+  NLAUNCHCHK();
   return STS_OK;
 }
 

@@ -36,7 +36,7 @@ void launch_cnn_loss(const CnnLaunch &L, const float *pred, const double *xs, co
 void launch_cnn_guess(const CnnLaunch &L, const double *T, const float *pred, double sd,
                       double *x0);
 void launch_cnn_adam(const CnnLaunch &L, int n, float *p, float *m, float *v, const float *g,
-                     const float *mask, float lr, int step);
+                     const float *mask, float lr, int step, float b1, float b2, float eps);
 void launch_cnn_make_frags(const CnnLaunch &L, const float *W, void *ffwd, void *fbwd);
 int cnn_moment_parts();
 void launch_cnn_moments(const CnnLaunch &L, const double *x, const double *y, double sc,
@@ -64,6 +64,7 @@ struct sts_cnn {
   double *d_out = nullptr;     // two device scalars read by the host
   double rhs_scale = 1.0, t_shift = 0.0, t_scale = 1.0, delta_scale = 1.0;
   int step = 0;                // Adam steps taken
+  float adam_b1 = 0.9f, adam_b2 = 0.999f, adam_eps = 1e-8f;  // Adam constants
 
   sts::CnnLaunch launch() const;
   void *act(int l) const { return (char *)d_act + (size_t)l * ncell * sts::kCnnC * 2; }

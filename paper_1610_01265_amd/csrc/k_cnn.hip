@@ -529,11 +529,11 @@ void launch_cnn_guess(const CnnLaunch &L, const double *T, const float *pred, do
 }
 
 void launch_cnn_adam(const CnnLaunch &L, int n, float *p, float *m, float *v, const float *g,
-              const float *mask, float lr, int step) {
-  const float b1 = 0.9f, b2 = 0.999f;
+                     const float *mask, float lr, int step, float b1, float b2, float eps) {
+  // bias corrections 1 - beta^t of this step t
   const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, L.stream, n, p, m, v, g, mask,
-                     lr, b1, b2, c1, c2, 1e-8f);
+                     lr, b1, b2, c1, c2, eps);
 }
 
 void launch_cnn_make_frags(const CnnLaunch &L, const float *W, void *ffwd, void *fbwd) {

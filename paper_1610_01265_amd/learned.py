@@ -46,15 +46,22 @@ def _temperature(args):
     return seed, temperature(rf, thf, phf, seed)
 
 
-def seeded_fields(shape, seeds, workers=8):
-    """(seed, T) for each seed, generated on the host in a process pool."""
+def host_fields(shape, seeds, workers=8):
+    """[(seed, T)] for each seed, generated on the host.  With workers > 1 the
+    fields come from a pool of fresh interpreter processes, which is started
+    only while this process has not initialised the GPU (a child started
+    from a process that holds the device would inherit it); otherwise, and
+    for short lists, they are generated here, one after another.  The pool's
+    workers finish their tasks and exit on their own (no terminate)."""
     seeds = list(seeds)
-    if workers <= 1 or len(seeds) < 4:
-        for s in seeds:
-            yield _temperature((shape, s))
-        return
-    with get_context("spawn").Pool(workers) as pool:
-        yield from pool.imap(_temperature, [(shape, s) for s in seeds])
+    if workers <= 1 or len(seeds) < 4 or torch.cuda.is_initialized():
+        return [_temperature((shape, s)) for s in seeds]
+    pool = get_context("spawn").Pool(min(workers, len(seeds)))
+    try:
+        return pool.map(_temperature, [(shape, s) for s in seeds])
+    finally:
+        pool.close()
+        pool.join()
 
 
 class Problem:
@@ -75,10 +82,10 @@ class Problem:
         return self.ctx.dt_euler()
 
 
-def make_pairs(prob: Problem, seeds, ratio=200.0, rtol=1e-10, maxit=20000, workers=8,
-               solve=True):
+def make_pairs(prob: Problem, fields, ratio=200.0, rtol=1e-10, maxit=20000, solve=True):
+    """Training pairs from host fields [(seed, T)] (host_fields)."""
     pairs = []
-    for seed, T_host in seeded_fields(prob.shape, seeds, workers):
+    for seed, T_host in fields:
         T = torch.from_numpy(T_host).cuda()
         dt = ratio * prob.set_temperature(T)
         F = prob.ctx.apply_F(T)
@@ -130,12 +137,12 @@ class GuessResult:
     used_net: bool = True
 
 
-def evaluate(prob: Problem, net: B.Cnn, seeds, ratio=200.0, rtol=1e-8, maxit=20000,
-             workers=8):
-    """Jacobi-PCG to rtol from the zero, previous-step and network guesses."""
+def evaluate(prob: Problem, net: B.Cnn, fields, ratio=200.0, rtol=1e-8, maxit=20000):
+    """Jacobi-PCG to rtol from the zero, previous-step and network guesses, on
+    host fields [(seed, T)] (host_fields)."""
     out = []
     ctx = prob.ctx
-    for seed, T_host in seeded_fields(prob.shape, seeds, workers):
+    for seed, T_host in fields:
         T = torch.from_numpy(T_host).cuda()
         dt = ratio * prob.set_temperature(T)
         res = GuessResult(seed)
@@ -169,14 +176,20 @@ def summary(results):
 
 def run(shape=(128, 128, 256), train_seeds=range(200), test_seeds=range(200, 250), ratio=200.0,
         epochs=4, lr=1e-3, init_seed=0, train_rtol=1e-10, rtol=1e-8, workers=8, log=print):
-    """The whole learned-guess protocol; returns (summary, per-seed results, timings)."""
+    """The whole learned-guess protocol; returns (summary, per-seed results, timings).
+    The host fields are generated first, before this call touches the GPU."""
     from workloads import flatten, he_normal
+    t = {}
+    t0 = time.perf_counter()
+    train_fields = host_fields(shape, train_seeds, workers)
+    test_fields = host_fields(shape, test_seeds, workers)
+    t["fields_s"] = time.perf_counter() - t0
     prob = Problem(shape)
     net = B.Cnn(prob.ctx)
     net.set_weights(flatten(he_normal(4, 16, init_seed)))
-    t = {}
     t0 = time.perf_counter()
-    pairs = make_pairs(prob, train_seeds, ratio, train_rtol, workers=workers)
+    pairs = make_pairs(prob, train_fields, ratio, train_rtol)
+    del train_fields
     t["pairs_s"] = time.perf_counter() - t0
     fit_norm(net, pairs)
     torch.cuda.synchronize()
@@ -186,7 +199,7 @@ def run(shape=(128, 128, 256), train_seeds=range(200), test_seeds=range(200, 250
     t["train_s"] = time.perf_counter() - t0
     t["train_steps"] = epochs * len(pairs)
     del pairs
-    results = evaluate(prob, net, test_seeds, ratio, rtol, workers=workers)
+    results = evaluate(prob, net, test_fields, ratio, rtol)
     s = summary(results)
     s["loss_per_epoch"] = hist
     return s, results, t, net, prob
@@ -206,7 +219,6 @@ def main(argv=None):
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--workers", type=int, default=8)
     a = ap.parse_args(argv)
-    torch.cuda.set_device(0)
     s, results, t, net, prob = run(tuple(a.shape), range(*a.train), range(*a.test), a.ratio,
                                    a.epochs, a.lr, rtol=a.rtol, workers=a.workers,
                                    log=lambda m: print(m, flush=True))

@@ -52,3 +52,27 @@ def test_arguments_parse(flag, monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py", flag, "3"])
     a = bench.parse()
     assert getattr(a, flag.lstrip("-").replace("-", "_")) == 3 and a.gpus == 1
+
+
+def test_cpu_baseline_slab_sample():
+    """Large grids are sampled by their innermost r-planes."""
+    from workloads import make_workload
+    w = make_workload("shell32")
+    rec = bench.cpu_baseline(w, 50.0, budget_s=0.0, max_steps=1, max_cells=8 * 32 * 64)
+    assert rec["value"] > 0
+    assert "the 8 innermost r-planes (8x32x64 = 16384 cells) of shell32" in rec["sample"]
+
+
+def test_median():
+    assert bench.median([3.0, 1.0, 2.0]) == 2.0
+    assert bench.median([4.0, 1.0, 3.0, 2.0]) == 2.5
+
+
+def test_host_fields_pool_equals_in_process():
+    """The training fields of the learned guess are the same whether a pool
+    of fresh processes or this process generates them."""
+    from paper_1610_01265_amd import learned
+    a = learned.host_fields((4, 6, 8), range(5), workers=2)
+    b = learned.host_fields((4, 6, 8), range(5), workers=1)
+    assert [s for s, _ in a] == list(range(5))
+    assert all(sa == sb and (ta == tb).all() for (sa, ta), (sb, tb) in zip(a, b))

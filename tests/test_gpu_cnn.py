@@ -237,63 +237,100 @@ def test_forward_matches_chain_and_oracle(gpu_lib, shape):
     torch.cuda.synchronize()
 
 
-def test_train_step_matches_chain_and_adam(gpu_lib):
-    """One cnn_train_step = forward, loss, back-propagation and Adam, checked
-    against the kernels called one by one and Adam written out in FP32."""
-    sts = gpu_lib
+def _chain_grads(sts, net, F, dt, T, xs, norm):
+    """Loss gradient of the network, kernel by kernel through the ABI:
+    (padded gradient per layer as device tensors, activations, loss)."""
     torch = _torch()
-    shape = (5, 8, 66)
-    ctx, net, params = _net(sts, shape, seed=11)
-    F, T, xs = _inputs(shape, 11)
-    dt, norm = 0.5, (1e-4, 1.2e6, 5e-6, 2e3)
-    net.set_norm(*norm)
-    w0 = net.get_weights()
     acts, pred = _chain_forward(sts, net, F, dt, T)
     n = T.size
     p = _host(pred)
     tgt = ((xs - T) * (1.0 / norm[3])).ravel()
     d = p - tgt
-    loss_ref = float(np.mean(d * d))
     g = np.zeros((n, 16), np.float32)
     g[:, 0] = (np.float32(2.0 / n) * d.astype(np.float32))
     gcur = torch.from_numpy(g).to(torch.bfloat16).cuda()
     grads = [None] * 4
     for l in range(3, -1, -1):
-        grads[l] = _host(net.weight_grad(l, acts[l], gcur))
+        grads[l] = net.weight_grad(l, acts[l], gcur)
         if l > 0:
             gcur = net.conv(l, sts.CNN_INPUT_GRAD, gcur, mask=acts[l])
+    return grads, acts, float(np.mean(d * d))
+
+
+def test_adam_step_matches_oracle(gpu_lib):
+    """cnn_adam_step against the oracle's Adam (FP64) over four steps with
+    varying gradients, beta1 = 0.5 != beta2 = 0.75 (a swap, a missing or
+    mis-timed bias correction moves the weights by O(lr)).  Gradients are
+    seeded FP32 values in the padded layout; padding entries are ignored."""
+    sts = gpu_lib
+    torch = _torch()
+    ctx, net, params = _net(sts, (2, 3, 4), seed=5)
+    b1, b2, eps, lr = 0.5, 0.75, 1e-8, 1e-3
+    net.set_adam(b1, b2, eps)
+    oparams = [[W.astype(np.float64).copy(), b.astype(np.float64).copy()] for W, b in params]
+    st = ocnn.adam_init(oparams)
+    rng = np.random.default_rng(42)
+    P = sts.CNN_PADDED_PARAMS
+    for t in range(4):
+        gpad = rng.standard_normal((4, P)).astype(np.float32)
+        grads = []
+        for l in range(4):
+            cin, cout = _dims(l)
+            gW = gpad[l, :16 * 16 * 27].reshape(16, 16, 3, 3, 3)[:cout, :cin]
+            grads.append([gW.astype(np.float64), gpad[l, 16 * 16 * 27:][:cout].astype(np.float64)])
+        net.adam_step(torch.from_numpy(gpad.ravel()).cuda(), lr)
+        st = ocnn.adam_step(oparams, grads, st, lr, beta1=b1, beta2=b2, eps=eps)
+        w = net.get_weights().astype(np.float64)
+        ref = flatten(oparams).astype(np.float64)
+        # FP32 master weights and FP32 arithmetic: an ulp of the weight per step
+        assert np.all(np.abs(w - ref) <= 2 * (t + 1) * np.spacing(np.abs(ref).astype(np.float32))
+                      + 1e-4 * lr), t
+    with pytest.raises(sts.StsError):
+        net.set_adam(1.0, 0.5)
+
+
+def test_train_steps_match_chain_and_adam_step(gpu_lib):
+    """Three cnn_train_step calls (forward, loss, back-propagation, Adam with
+    beta1 = 0.5, beta2 = 0.75) on different samples, against a second network
+    driven by the kernels one by one and cnn_adam_step; the first step's
+    gradients also against the oracle's back-propagation."""
+    sts = gpu_lib
+    shape = (5, 8, 66)
+    ctx, net, params = _net(sts, shape, seed=11)
+    ctx2 = _ctx(sts, shape)
+    net2 = sts.Cnn(ctx2, 4)
+    net2.set_weights(flatten(params))
+    dt, norm = 0.5, (1e-4, 1.2e6, 5e-6, 2e3)
     lr = 1e-3
-    loss = net.train_step(_cuda(F), dt, _cuda(T), _cuda(xs), lr)
-    w1 = net.get_weights()
-    assert loss == pytest.approx(loss_ref, rel=1e-6)
-    # expected first Adam step on the padded gradients, unpadded to the ABI order
-    from workloads import unflatten
-    ref = []
-    for l, (W, b) in enumerate(unflatten(w0)):
-        cin, cout = _dims(l)
-        gW = grads[l][:16 * 16 * 27].reshape(16, 16, 3, 3, 3)[:cout, :cin]
-        gb = grads[l][16 * 16 * 27:][:cout]
-        for P, G in ((W, gW), (b, gb)):
-            G = G.astype(np.float32)
-            one, b1, b2 = np.float32(1), np.float32(0.9), np.float32(0.999)
-            m = (one - b1) * G
-            v = (one - b2) * G * G
-            step = (m / (one - b1)) / (np.sqrt(v / (one - b2)) + np.float32(1e-8))
-            ref.append((P.astype(np.float32) - np.float32(lr) * step).ravel())
-    ref = np.concatenate(ref)
-    # FP32 on both sides; fused multiply-adds on the GPU: a few ulps
-    assert np.all(np.abs(w1 - ref) <= 4 * np.spacing(np.abs(ref)) + 1e-4 * lr)
-    # the gradients against the oracle's back-propagation through the same
-    # network (bf16 activation rounding on both sides)
-    xin = np.stack([RB(F * (dt * norm[0])), RB((T - norm[1]) * norm[2])])
-    y, cache = ocnn.forward(params, xin, act_round=RB)
-    _, dy = ocnn.mse_loss(y, ((xs - T) / norm[3])[None])
-    og = ocnn.backward(params, cache, dy)
-    for l in range(4):
-        cin, cout = _dims(l)
-        gW = grads[l][:16 * 16 * 27].reshape(16, 16, 3, 3, 3)[:cout, :cin]
-        err = np.linalg.norm(gW - og[l][0]) / np.linalg.norm(og[l][0])
-        assert err < 2e-2, (l, err)
+    for nn in (net, net2):
+        nn.set_norm(*norm)
+        nn.set_adam(0.5, 0.75)
+    for t in range(3):
+        F, T, xs = _inputs(shape, 11 + t)
+        grads, acts, loss_ref = _chain_grads(sts, net2, F, dt, T, xs, norm)
+        loss = net.train_step(_cuda(F), dt, _cuda(T), _cuda(xs), lr)
+        assert loss == pytest.approx(loss_ref, rel=1e-6)
+        _torch().cuda.synchronize()
+        net2.adam_step(_torch().cat(grads), lr)
+        w1, w2 = net.get_weights(), net2.get_weights()
+        # FP32 on both sides; the loss gradient is formed on the host on one
+        # side: a few ulps per step
+        assert np.all(np.abs(w1 - w2) <= 4 * (t + 1) * np.spacing(np.abs(w2)) + 1e-4 * lr), t
+        if t == 0:
+            # the gradients against the oracle's back-propagation through the
+            # same network (bf16 activation rounding on both sides)
+            xin = np.stack([RB(F * (dt * norm[0])), RB((T - norm[1]) * norm[2])])
+            y, cache = ocnn.forward(params, xin, act_round=RB)
+            _, dy = ocnn.mse_loss(y, ((xs - T) / norm[3])[None])
+            og = ocnn.backward(params, cache, dy)
+            for l in range(4):
+                cin, cout = _dims(l)
+                gh = _host(grads[l])
+                gW = gh[:16 * 16 * 27].reshape(16, 16, 3, 3, 3)[:cout, :cin]
+                err = np.linalg.norm(gW - og[l][0]) / np.linalg.norm(og[l][0])
+                assert err < 2e-2, (l, err)
+    net2.close()
+    ctx2.close()
 
 
 def test_training_reduces_loss(gpu_lib):

@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass, field
-from multiprocessing import get_context
+from multiprocessing.pool import ThreadPool
 
 import numpy as np
 import torch
@@ -47,21 +47,15 @@ def _temperature(args):
 
 
 def host_fields(shape, seeds, workers=8):
-    """[(seed, T)] for each seed, generated on the host.  With workers > 1 the
-    fields come from a pool of fresh interpreter processes, which is started
-    only while this process has not initialised the GPU (a child started
-    from a process that holds the device would inherit it); otherwise, and
-    for short lists, they are generated here, one after another.  The pool's
-    workers finish their tasks and exit on their own (no terminate)."""
+    """[(seed, T)] for each seed, generated on the host by a pool of threads
+    of this process (numpy's generators and array passes release the
+    interpreter lock, so the threads run in parallel).  No child process is
+    ever started, whether or not this process holds the GPU."""
     seeds = list(seeds)
-    if workers <= 1 or len(seeds) < 4 or torch.cuda.is_initialized():
+    if workers <= 1 or len(seeds) < 4:
         return [_temperature((shape, s)) for s in seeds]
-    pool = get_context("spawn").Pool(min(workers, len(seeds)))
-    try:
+    with ThreadPool(min(workers, len(seeds))) as pool:
         return pool.map(_temperature, [(shape, s) for s in seeds])
-    finally:
-        pool.close()
-        pool.join()
 
 
 class Problem:

@@ -124,6 +124,23 @@ sts_status apply_F(sts_ctx *ctx, const double *u, double *Fu, int ncomp);
  * receives s.  Each stage is one fused stencil + recurrence kernel.  */
 sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used);
 
+/* rkl2_step_noalloc - rkl2_step for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results (bit for bit) and kernels as
+ * rkl2_step; the stage buffers (F0 and two state arrays in FP64, or F0 and two
+ * FP32 increments in the precision form) live in a static device array of
+ * 96 MiB that each GPU holds from sts_create until the process ends, so the
+ * call allocates nothing.  Limits and errors:
+ *  - ncell * ncomp <= 4,194,304 in FP64 (8,388,608 in the FP32 form), else
+ *    STS_EINVAL (nothing enqueued);
+ *  - s <= 0 needs dt_E already computed for the current operator (a prior
+ *    sts_dt_euler, rkl2_step or rkl_step call), else STS_EINVAL;
+ *  - STS_EHIP if the array's device address could not be resolved.
+ * The array is shared by every context on one GPU and keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap in
+ * time on one GPU (other streams, other threads) race.  */
+sts_status rkl2_step_noalloc(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used);
+
 /* rkl_step - the super-step with the variants discussed in Sec. 6 (with
  * Fig. "ampfac") and after Eq. rkl2_s, in this order:
  *   euler_fraction in [0, 1): first advance euler_fraction * dt by explicit

@@ -55,6 +55,7 @@ def load():
         "sts_dt_euler": (I, [P, PD]),
         "apply_F": (I, [P, P, P, I]),
         "rkl2_step": (I, [P, P, I, D, I, PI]),
+        "rkl2_step_noalloc": (I, [P, P, I, D, I, PI]),
         "rkl_step": (I, [P, P, I, D, I, I, I, I, D, D, PI]),
         "apply_F_nonlinear": (I, [P, P, P, D, P, P, P]),
         "rkl2_step_nonlinear": (I, [P, P, D, D, P, P, P, I, PI]),
@@ -92,8 +93,8 @@ def load():
 def exported_symbols():
     return ["sts_create", "sts_destroy", "sts_set_stream", "sts_last_error", "sts_num_cells",
             "sts_set_spitzer", "sts_set_isotropic", "sts_set_spitzer_f32", "sts_set_isotropic_f32",
-            "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "rkl_step",
-            "apply_F_nonlinear", "rkl2_step_nonlinear", "sts_set_resistivity",
+            "sts_set_dirichlet", "sts_dt_euler", "apply_F", "rkl2_step", "rkl2_step_noalloc",
+            "rkl_step", "apply_F_nonlinear", "rkl2_step_nonlinear", "sts_set_resistivity",
             "sts_resistivity_sizes", "apply_F_resistivity", "resistivity_dt_euler",
             "resistivity_be_pcg_solve", "be_pcg_solve",
             "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
@@ -220,6 +221,16 @@ class Context:
         used = ctypes.c_int()
         self._check(self._lib.rkl2_step(self._h, _ptr(u, self.ncell, "u", nc), nc, float(dt),
                                         int(s), ctypes.byref(used)))
+        return used.value
+
+    def rkl2_step_noalloc(self, u, dt, s=0) -> int:
+        """rkl2_step with its stage buffers in the library's static device
+        scratch (no device allocation; see include/sts.h for the limits)."""
+        self._sync_stream()
+        nc = self._ncomp(u)
+        used = ctypes.c_int()
+        self._check(self._lib.rkl2_step_noalloc(self._h, _ptr(u, self.ncell, "u", nc), nc,
+                                                float(dt), int(s), ctypes.byref(used)))
         return used.value
 
     def rkl_step(self, u, dt, scheme=2, extra=0, odd=False, nsub=1, euler_fraction=0.0,
@@ -494,6 +505,10 @@ def apply_F(ctx: Context, u, out=None):
 
 def rkl2_step(ctx: Context, u, dt, s=0) -> int:
     return ctx.rkl2_step(u, dt, s)
+
+
+def rkl2_step_noalloc(ctx: Context, u, dt, s=0) -> int:
+    return ctx.rkl2_step_noalloc(u, dt, s)
 
 
 def apply_F_nonlinear(ctx: Context, u, kappa0, b0, b1, b2, out=None):

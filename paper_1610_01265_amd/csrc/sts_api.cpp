@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "sts_internal.h"
@@ -117,6 +119,38 @@ constexpr int kMaxStages = 1 << 20;
 constexpr int kPollEvery = 8;  // PCG iterations enqueued between host polls
 constexpr int kRkBuffers = 2;  // RKL2 state buffers besides F0
 
+// Scratch of rkl2_step_noalloc: a file-scope device array, one copy per GPU,
+// held until the process ends.  Host code never passes its name to a kernel
+// (in host code the name is a host-side stand-in): the device address is
+// resolved once per device with hipGetSymbolAddress and used from there on.
+constexpr size_t kScratchBytes = (size_t)96 << 20;  // 4,194,304 FP64 cells x components
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_st[kMaxDevices];
+static bool g_scratch_done[kMaxDevices];
+
+// Device address of `scratch` on the current device (resolved at the first
+// call on that device); nullptr with err set on failure.
+static void *scratch_address(int device, std::string *err) {
+  if (device < 0 || device >= kMaxDevices) {
+    *err = "device index out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void *ptr = nullptr;
+    g_scratch_st[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = g_scratch_st[device] == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
+  }
+  if (!g_scratch_ptr[device])
+    *err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(g_scratch_st[device]);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -167,6 +201,7 @@ sts_status sts_create(sts_ctx **out, int coord, int n0, int n1, int n2, const do
     delete ctx;
     return STS_EHIP;
   }
+  ctx->d_scratch = scratch_address(ctx->device, &ctx->scratch_err);
 
   // --- separable geometry tables ---
   std::vector<double> t0((size_t)NT0 * n0), t1((size_t)NT1 * n1), t2((size_t)NT2 * n2);
@@ -453,16 +488,20 @@ sts_status apply_F(sts_ctx *ctx, const double *u, double *Fu, int ncomp) {
 //   delta_k = mu_k delta_{k-1} + nu_k delta_{k-2} + mu~_k dt M delta_{k-1}
 //             + (mu~_k + gamma~_k) dt F0,
 // (F affine: F(u_{k-1}) = F0 + M delta_{k-1}), u^{n+1} = u_0 + delta_s in FP64.
-static sts_status rkl2_step_f32(sts_ctx *ctx, double *u, int ncomp, double dt, int s) {
+// ws: 3 * ncell * ncomp floats of workspace, or nullptr for the context's own
+// (allocated at the first call that needs it).
+static sts_status rkl2_step_f32(sts_ctx *ctx, double *u, int ncomp, double dt, int s,
+                                float *ws = nullptr) {
   const long long n = ctx->ncell * ncomp;
-  if (ctx->rk32_ncomp < ncomp) {
+  if (!ws && ctx->rk32_ncomp < ncomp) {
     dfree(ctx->d_rk32);
     ctx->rk32_ncomp = 0;
     sts_status st = dalloc(ctx, (void **)&ctx->d_rk32, (size_t)3 * n * 4);
     if (st) return st;
     ctx->rk32_ncomp = ncomp;
   }
-  float *F0 = ctx->d_rk32, *Da = ctx->d_rk32 + n, *Db = ctx->d_rk32 + 2 * n;
+  float *const W = ws ? ws : ctx->d_rk32;
+  float *F0 = W, *Da = W + n, *Db = W + 2 * n;
   const double ss = (double)s * s + s - 2.0;
   auto bk = [](int k) { return k <= 2 ? 1.0 / 3.0 : ((double)k * k + k - 2.0) / (2.0 * k * (k + 1.0)); };
   const double w1 = 4.0 / ss;
@@ -508,14 +547,19 @@ struct NlSpitzer {
 
 // One super-step of s stages in FP64: scheme 2 = RKL2 (Sec. 3, Fig. "rkl2"),
 // scheme 1 = RKL1 (the first-order member of the same family).
+// ws: (1 + kRkBuffers) * ncell * ncomp doubles of workspace, or nullptr for the
+// context's own (allocated at the first call that needs it).
 static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int scheme,
-                          const NlSpitzer *nl = nullptr) {
-  sts_status st0 = rk_workspace(ctx, ncomp);
-  if (st0) return st0;
+                          const NlSpitzer *nl = nullptr, double *ws = nullptr) {
+  if (!ws) {
+    sts_status st0 = rk_workspace(ctx, ncomp);
+    if (st0) return st0;
+  }
   const long long n = ctx->ncell * ncomp;
-  double *F0 = ctx->d_rk;
+  double *const W = ws ? ws : ctx->d_rk;
+  double *F0 = W;
   double *P[kRkBuffers];
-  for (int q = 0; q < kRkBuffers; ++q) P[q] = ctx->d_rk + (1 + q) * n;
+  for (int q = 0; q < kRkBuffers; ++q) P[q] = W + (1 + q) * n;
   // stage coefficients (Sec. 3): b_k, mu_k, nu_k, mu~_k, gamma~_k
   const double ss = (double)s * s + s - 2.0;
   auto bk = [](int k) { return k <= 2 ? 1.0 / 3.0 : ((double)k * k + k - 2.0) / (2.0 * k * (k + 1.0)); };
@@ -575,24 +619,57 @@ static sts_status rk_fp64(sts_ctx *ctx, double *u, int ncomp, double dt, int s, 
   return STS_OK;
 }
 
-sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used) {
+// Argument checks and the stage count shared by rkl2_step and
+// rkl2_step_noalloc.  With need_cached_dte, s <= 0 requires dt_E to have
+// been computed already (its reduction may allocate).
+static sts_status rkl2_prepare(sts_ctx *ctx, const char *name, double *u, int ncomp, double dt,
+                               int *s, bool need_cached_dte) {
   if (!ctx) return STS_EINVAL;
+  const std::string nm(name);
   if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
-  if (!u) FAIL(STS_EINVAL, "rkl2_step: null u");
-  if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, "rkl2_step: ncomp must be in [1, 16]");
-  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "rkl2_step: dt must be finite, > 0");
-  if (s <= 0) {
+  if (!u) FAIL(STS_EINVAL, nm + ": null u");
+  if (ncomp < 1 || ncomp > 16) FAIL(STS_EINVAL, nm + ": ncomp must be in [1, 16]");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, nm + ": dt must be finite, > 0");
+  if (*s <= 0) {
+    if (need_cached_dte && !(ctx->dt_euler > 0))
+      FAIL(STS_EINVAL, nm + ": s <= 0 needs dt_E, not yet computed for this operator "
+                            "(call sts_dt_euler first)");
     double dte;
     sts_status st = sts_dt_euler(ctx, &dte);
     if (st) return st;
     const double ratio = dt / dte;
     if (!(ratio < 0.25 * kMaxStages * (double)kMaxStages)) FAIL(STS_EINVAL, "dt too large");
-    s = stage_count(ratio);
+    *s = stage_count(ratio);
   }
-  if (s < 2 || s > kMaxStages) FAIL(STS_EINVAL, "rkl2_step: s must be >= 2");
+  if (*s < 2 || *s > kMaxStages) FAIL(STS_EINVAL, nm + ": s must be >= 2");
+  return STS_OK;
+}
+
+sts_status rkl2_step(sts_ctx *ctx, double *u, int ncomp, double dt, int s, int *s_used) {
+  sts_status st = rkl2_prepare(ctx, "rkl2_step", u, ncomp, dt, &s, false);
+  if (st) return st;
   if (s_used) *s_used = s;
   if (ctx->prec == 1) return rkl2_step_f32(ctx, u, ncomp, dt, s);
   return rk_fp64(ctx, u, ncomp, dt, s, 2);
+}
+
+sts_status rkl2_step_noalloc(sts_ctx *ctx, double *u, int ncomp, double dt, int s,
+                             int *s_used) {
+  sts_status st = rkl2_prepare(ctx, "rkl2_step_noalloc", u, ncomp, dt, &s, true);
+  if (st) return st;
+  if (!ctx->d_scratch)
+    FAIL(STS_EHIP, "rkl2_step_noalloc: the static scratch array has no device address: " +
+                       ctx->scratch_err);
+  const long long n = ctx->ncell * ncomp;
+  const long long need = ctx->prec == 1 ? 3 * n * 4 : (long long)(1 + kRkBuffers) * n * 8;
+  if (need > (long long)kScratchBytes)
+    FAIL(STS_EINVAL, "rkl2_step_noalloc: needs " + std::to_string(need) +
+                         " bytes of scratch, above its " + std::to_string(kScratchBytes) +
+                         " (at most " + std::to_string(kScratchBytes / (ctx->prec == 1 ? 12 : 24)) +
+                         " cells x components)");
+  if (s_used) *s_used = s;
+  if (ctx->prec == 1) return rkl2_step_f32(ctx, u, ncomp, dt, s, (float *)ctx->d_scratch);
+  return rk_fp64(ctx, u, ncomp, dt, s, 2, nullptr, (double *)ctx->d_scratch);
 }
 
 

@@ -94,6 +94,8 @@ struct sts_ctx {
   double *d_rk = nullptr;     // RKL2: F0 and 2 (4 with fused stages) state buffers
   int rk_ncomp = 0;
   float *d_rk32 = nullptr;    // FP32 form RKL2: F0, delta_a, delta_b
+  void *d_scratch = nullptr;  // device address of the static scratch array (not owned)
+  std::string scratch_err;    // why d_scratch is null, if it is
   int rk32_ncomp = 0;
   float *d_pcg32 = nullptr;   // FP32 form PCG: 1/A_ii, e, r, p0, p1, y, z
   double *d_pcg = nullptr;    // PCG vectors

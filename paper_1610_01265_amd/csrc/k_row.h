@@ -84,6 +84,26 @@ struct RowCoef {
   R K01[4], K02[4], K12[4];
 };
 
+// Dirichlet faces of a cell on a Dirichlet side of axis 0: -w_b u_c, plus the
+// boundary term g_c = w_b u_b when WITH_G.
+template <bool WITH_G, class R, class CT>
+__device__ __forceinline__ R dirichlet_terms(const Grid &g, const CoefS<CT> &C, int i, int j,
+                                             int k, R u0) {
+  R acc = R(0);
+  if ((g.dir_lo && i == 0) || (g.dir_hi && i == g.n0 - 1)) {
+    const int bi = j * g.n2 + k;
+    const bool lo = g.dir_lo && i == 0;
+    const R wb = lo ? C.wb_lo[bi] : C.wb_hi[bi];
+    const R ub = lo ? C.ub_lo[bi] : C.ub_hi[bi];
+    acc = WITH_G ? wb * (ub - u0) : -wb * u0;
+    if (g.dir_lo && g.dir_hi && i == 0 && i == g.n0 - 1) {  // single radial cell
+      const R wh = C.wb_hi[bi], uh = C.ub_hi[bi];
+      acc += WITH_G ? wh * (uh - u0) : -wh * u0;
+    }
+  }
+  return acc;
+}
+
 // (S u)_c (+ g_c when WITH_G), u read through U(di, dj, dk); arithmetic in R.
 template <int OP, bool WITH_G, class R, class CT, class UF>
 __device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const RowCoef<R> &W,
@@ -148,15 +168,82 @@ __device__ __forceinline__ R apply_S(const Grid &g, const CoefS<CT> &C, const Ro
     acc += w2p * (U(0, 0, 1) - u0) + (tg.C.hm ? w2m : zero) * (U(0, 0, -1) - u0);
     acc *= R(C.nu);
   }
-  if ((g.dir_lo && i == 0) || (g.dir_hi && i == g.n0 - 1)) {
-    const int bi = j * g.n2 + k;
-    const bool lo = g.dir_lo && i == 0;
-    const R wb = lo ? C.wb_lo[bi] : C.wb_hi[bi];
-    const R ub = lo ? C.ub_lo[bi] : C.ub_hi[bi];
-    acc += WITH_G ? wb * (ub - u0) : -wb * u0;
-    if (g.dir_lo && g.dir_hi && i == 0 && i == g.n0 - 1) {  // single radial cell
-      const R wh = C.wb_hi[bi], uh = C.ub_hi[bi];
-      acc += WITH_G ? wh * (uh - u0) : -wh * u0;
+  return acc + dirichlet_terms<WITH_G, R, CT>(g, C, i, j, k, u0);
+}
+
+// The march form of the conduction row.  The terms that join plane ip to
+// plane ip + 1 in the column of cell (j, k) -- its +r face and the four edges
+// of the (r, theta) and (r, phi) planes with origin (ip, j - q, k) and
+// (ip, j, k - q), q = 0, 1 -- are evaluated once, for both cells they touch:
+// `lo` is their part of (S u) for the cell of plane ip, `hi` their part for
+// the cell of plane ip + 1 (added to that cell's row when the march reaches
+// it).  With X' = (u10 - u00) + (u11 - u01) and Y' = (u01 - u00)/dl_b(e00) +
+// (u11 - u10)/dl_b(e10), an edge adds K/(4 dl_a) [s_a Y' + s_b X'/dl_b(face)]
+// to each of its cells (the edge term of the energy form, with dl_a the same
+// for both a-faces of an (r, .) or (theta, phi) edge).  Ul(dj, dk) reads plane
+// ip, Uh(dj, dk) plane ip + 1; K01q[q], K02q[q] are the edge coefficients,
+// already zero for absent edges; qia = 1/(4 dl_r(ip)).
+template <class R, class UL, class UH>
+__device__ __forceinline__ void r_terms(const UL &Ul, const UH &Uh, R w, const R K01q[2],
+                                        const R K02q[2], R qia, R s10lo, R s10hi, R s20lo,
+                                        R s20hi, const ThreadGeo<R> &tg, R &lo, R &hi) {
+  const R f = w * (Uh(0, 0) - Ul(0, 0));
+  lo = f;
+  hi = -f;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    // (r, theta) edge, origin row j - q
+    {
+      const R a00 = Ul(-q, 0), a01 = Ul(1 - q, 0), a10 = Uh(-q, 0), a11 = Uh(1 - q, 0);
+      const R tj = q ? tg.t11m : tg.t11;
+      const R ib0 = s10lo * tj, ib1 = s10hi * tj;
+      const R X = (a10 - a00) + (a11 - a01);
+      const R Y = (a01 - a00) * ib0 + (a11 - a10) * ib1;
+      const R t = K01q[q] * qia;
+      lo += t * (q ? Y - ib0 * X : Y + ib0 * X);
+      hi -= t * (q ? Y + ib1 * X : Y - ib1 * X);
+    }
+    // (r, phi) edge, origin column k - q
+    {
+      const R a00 = Ul(0, -q), a01 = Ul(0, 1 - q), a10 = Uh(0, -q), a11 = Uh(0, 1 - q);
+      const R tk = tg.t21 * (q ? tg.t22m : tg.t22);
+      const R ib0 = s20lo * tk, ib1 = s20hi * tk;
+      const R X = (a10 - a00) + (a11 - a01);
+      const R Y = (a01 - a00) * ib0 + (a11 - a10) * ib1;
+      const R t = K02q[q] * qia;
+      lo += t * (q ? Y - ib0 * X : Y + ib0 * X);
+      hi -= t * (q ? Y + ib1 * X : Y - ib1 * X);
+    }
+  }
+}
+
+// The in-plane part of the conduction row of cell (i, j, k): its theta and
+// phi faces and the four (theta, phi) edges around it.  U(dj, dk) reads plane
+// i; W.K12 holds the edge coefficients in the order of RowCoef (absent edges
+// masked here); s10 = 1/r_i-factor of dl_theta, s20 that of dl_phi.
+template <class R, class UF>
+__device__ __forceinline__ R inplane_S(const RowCoef<R> &W, const UF &U, R s10, R s20,
+                                       const ThreadGeo<R> &tg) {
+  const R u0 = U(0, 0);
+  const R zero = R(0);
+  R acc = W.w1p * (U(1, 0) - u0) + (tg.B.hm ? W.w1m : zero) * (U(-1, 0) - u0);
+  acc += W.w2p * (U(0, 1) - u0) + (tg.C.hm ? W.w2m : zero) * (U(0, -1) - u0);
+  const R qs = R(0.25) * s10 * s20;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const R cp = qs * (p ? tg.t11m : tg.t11);  // s20 / (4 dl_theta)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const bool ex = (p ? tg.B.hm : tg.B.hp) && (q ? tg.C.hm : tg.C.hp);
+      const R u00 = U(-p, -q), u10 = U(1 - p, -q), u01 = U(-p, 1 - q), u11 = U(1 - p, 1 - q);
+      const R tk = q ? tg.t22m : tg.t22;
+      const R P0 = (p ? tg.t21m : tg.t21) * tk, P1 = (p ? tg.t21 : tg.t21p) * tk;
+      const R X = (u10 - u00) + (u11 - u01);
+      const R Y = (u01 - u00) * P0 + (u11 - u10) * P1;
+      const R Pp = p ? P1 : P0;
+      const R t = (ex ? W.K12[p + 2 * q] : zero) * cp;
+      const R v = q ? -(Pp * X) : Pp * X;
+      acc += t * (p ? v - Y : v + Y);
     }
   }
   return acc;

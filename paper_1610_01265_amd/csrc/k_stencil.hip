@@ -178,6 +178,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   tg.t22m = T2(g, T_IL22, tg.C.m);
   tg.t22 = T2(g, T_IL22, kc);
   tg.v12 = T1(g, T_V1, jc) * T2(g, T_V2, kc);
+  const R iv12 = R(1) / tg.v12;
   tg.dJm = (tg.B.m - jc) * g.n2;
   tg.dKm = tg.C.m - kc;
   if (OP == OP_ISOTROPIC) {
@@ -258,10 +259,16 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     load_own(ip, L);
     load_nbr(ip, L);
   };
-  // coefficients of the previous plane (at the chunk start: loaded)
+  // Conduction: the part of the row of the cell of plane i that the faces and
+  // edges joining planes i - 1 and i contribute, evaluated with plane i - 1
+  // (r_terms) and carried in a register.  At the chunk start it is formed
+  // here from plane i0 - 1 (its coefficients loaded, its u in the ring).
+  const int base = (tj + 1) * HK + (tk + 1);
+  R carry = R(0);
   R pw0 = R(0), pk01 = R(0), pk02 = R(0), pk01B = R(0), pk02C = R(0);
-  if (OP == OP_SPITZER) {
-    const int cA = (nbr(i0, g.n0, g.per0).m * g.n1 + jc) * g.n2 + kc;
+  const Nb A0 = nbr(i0, g.n0, g.per0);
+  if (OP == OP_SPITZER && A0.hm) {
+    const int cA = (A0.m * g.n1 + jc) * g.n2 + kc;
     pw0 = R(C.w0[cA]);
     pk01 = R(C.k01[cA]);
     pk02 = R(C.k02[cA]);
@@ -271,6 +278,18 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   Loads cur;
   double acc_a = 0.0, acc_b = 0.0;
   __syncthreads();
+  if (OP == OP_SPITZER && A0.hm && active) {
+    const R *sl = s_u[(i0 - 1) & 3], *sh = s_u[i0 & 3];
+    auto Ul = [&](int dj, int dk) -> R { return sl[base + dj * HK + dk]; };
+    auto Uh = [&](int dj, int dk) -> R { return sh[base + dj * HK + dk]; };
+    const int ip = A0.m;
+    const R K01q[2] = {tg.B.hp ? pk01 : R(0), tg.B.hm ? pk01B : R(0)};
+    const R K02q[2] = {tg.C.hp ? pk02 : R(0), tg.C.hm ? pk02C : R(0)};
+    R lo;
+    r_terms<R>(Ul, Uh, pw0, K01q, K02q, R(0.25) * R(T0u(g, T_IL00, ip)), R(T0u(g, T_IL10, ip)),
+               R(T0u(g, T_IL10, i0)), R(T0u(g, T_IL20, ip)), R(T0u(g, T_IL20, i0)), tg, lo,
+               carry);
+  }
 
   for (int i = i0; i < i1; ++i) {
     const bool pre = i + 2 <= i1;
@@ -285,22 +304,17 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     if (active) {
       PlaneGeo<R> pg;
       pg.A = nbr(i, g.n0, g.per0);
-      pg.s00m = T0u(g, T_IL00, pg.A.m);
       pg.s00 = T0u(g, T_IL00, i);
-      pg.s10m = T0u(g, T_IL10, pg.A.m);
       pg.s10 = T0u(g, T_IL10, i);
-      pg.s10p = T0u(g, T_IL10, pg.A.p);
-      pg.s20m = T0u(g, T_IL20, pg.A.m);
       pg.s20 = T0u(g, T_IL20, i);
-      pg.s20p = T0u(g, T_IL20, pg.A.p);
       pg.v0 = T0u(g, T_V0, i);
       if (OP == OP_ISOTROPIC) {
+        pg.s00m = T0u(g, T_IL00, pg.A.m);
         pg.a00 = T0u(g, T_A00, i);
         pg.a00m = T0u(g, T_A00, pg.A.m);
         pg.a10 = T0u(g, T_A10, i);
         pg.a20 = T0u(g, T_A20, i);
       }
-      const int base = (tj + 1) * HK + (tk + 1);
       const R *sm = s_u[(i - 1) & 3], *s0 = s_u[i & 3], *sp = s_u[(i + 1) & 3];
       auto U = [&](int di, int dj, int dk) -> R {
         const R *s = di < 0 ? sm : (di > 0 ? sp : s0);
@@ -308,20 +322,10 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
       };
       RowCoef<R> W;
       if (OP == OP_SPITZER) {
-        W.w0p = cur.w0;
-        W.w0m = pw0;
         W.w1p = cur.w1;
         W.w1m = cur.w1B;
         W.w2p = cur.w2;
         W.w2m = cur.w2C;
-        W.K01[0] = cur.k01;
-        W.K01[1] = pk01;
-        W.K01[2] = cur.k01B;
-        W.K01[3] = pk01B;
-        W.K02[0] = cur.k02;
-        W.K02[1] = pk02;
-        W.K02[2] = cur.k02C;
-        W.K02[3] = pk02C;
         W.K12[0] = cur.k12;
         W.K12[1] = cur.k12B;
         W.K12[2] = cur.k12C;
@@ -330,28 +334,44 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
       const int c = (i * g.n1 + j) * g.n2 + k;
       const long long cc = off + c;
       constexpr bool with_g = MODE == M_F || MODE == M_RK1 || MODE == M_RK || MODE == M_F0F;
-      const R su = apply_S<OP, with_g, R, CT>(g, C, W, U, i, j, k, pg, tg);
+      R su;
+      if (OP == OP_SPITZER) {
+        auto Ul = [&](int dj, int dk) -> R { return s0[base + dj * HK + dk]; };
+        auto Uh = [&](int dj, int dk) -> R { return sp[base + dj * HK + dk]; };
+        const bool hp = pg.A.hp;
+        const R K01q[2] = {hp && tg.B.hp ? cur.k01 : R(0), hp && tg.B.hm ? cur.k01B : R(0)};
+        const R K02q[2] = {hp && tg.C.hp ? cur.k02 : R(0), hp && tg.C.hm ? cur.k02C : R(0)};
+        R lo, hi;
+        r_terms<R>(Ul, Uh, cur.w0, K01q, K02q, R(0.25) * pg.s00, pg.s10,
+                   R(T0u(g, T_IL10, pg.A.p)), pg.s20, R(T0u(g, T_IL20, pg.A.p)), tg, lo, hi);
+        su = carry + lo + inplane_S<R>(W, Ul, pg.s10, pg.s20, tg) +
+             dirichlet_terms<with_g, R, CT>(g, C, i, j, k, s0[base]);
+        carry = hi;
+      } else {
+        su = apply_S<OP, with_g, R, CT>(g, C, W, U, i, j, k, pg, tg);
+      }
       const R V = pg.v0 * tg.v12;
+      const R iV = R(T0u(g, T_IV0, i)) * iv12;
       const R uc = s0[base];
       if (MODE == M_F) {
-        ((R *)a.out)[cc] = su / V;
+        ((R *)a.out)[cc] = su * iV;
       } else if (MODE == M_F0F) {
-        const float F = (float)(su / V);
+        const float F = (float)(su * iV);
         ((float *)a.F0)[cc] = F;
         if (a.out) ((float *)a.out)[cc] = (float)a.mut_dt * F;  // delta_1 = mu~_1 dt F0
       } else if (MODE == M_RK1) {
-        const R F = su / V;
+        const R F = su * iV;
         stream_st(&((R *)a.F0)[cc], F);
         stream_st(&((R *)a.out)[cc], uc + R(a.mut_dt) * F);
       } else if (MODE == M_RK) {
-        const R F = su / V;
+        const R F = su * iV;
         st_a = R(a.mu) * uc + R(a.nu) * cur.x0 + (R(1) - R(a.mu) - R(a.nu)) * R(cur.x1) +
                R(a.mut_dt) * F + R(a.gt_dt) * cur.x2;
         st_c = cc;
       } else if (MODE == M_DK || MODE == M_DLAST) {
         // delta_k = mu delta_{k-1} + nu delta_{k-2} + mu~ dt M delta_{k-1}
         //           + (mu~ + gamma~) dt F0      (gt_dt carries (mu~ + gamma~) dt)
-        const R d = R(a.mu) * uc + R(a.nu) * cur.x0 + R(a.mut_dt) * (su / V) +
+        const R d = R(a.mu) * uc + R(a.nu) * cur.x0 + R(a.mut_dt) * (su * iV) +
                     R(a.gt_dt) * cur.x2;
         if (MODE == M_DK)
           ((R *)a.out)[cc] = d;
@@ -374,13 +394,6 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
         acc_a += rv * rv;
         acc_b += bv * bv;
       }
-    }
-    if (OP == OP_SPITZER) {
-      pw0 = cur.w0;
-      pk01 = cur.k01;
-      pk02 = cur.k02;
-      pk01B = cur.k01B;
-      pk02C = cur.k02C;
     }
     if (pre) store_plane(i + 2, v);
     if (MODE == M_RK && active) stream_st(&((R *)a.out)[st_c], st_a);

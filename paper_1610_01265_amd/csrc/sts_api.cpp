@@ -228,6 +228,7 @@ sts_status sts_create(sts_ctx **out, int coord, int n0, int n1, int n2, const do
       T[T_IL20 * n0 + i] = 1.0;
     }
     T[T_IL00 * n0 + i] = ig0[i];
+    T[T_IV0 * n0 + i] = 1.0 / T[T_V0 * n0 + i];
   }
   for (int j = 0; j < n1; ++j) {
     const double a = f1[j], b = f1[j + 1], c = 0.5 * (a + b), d = b - a;

@@ -24,7 +24,7 @@ namespace sts {
 // non-periodic axis).  Dirichlet faces on axis 0: area AB[s] A01[j] A02[k],
 // centre-to-face distance DB[s].
 // ---------------------------------------------------------------------------
-enum Tab0 { T_V0, T_A00, T_A10, T_A20, T_IL00, T_IL10, T_IL20, NT0 };
+enum Tab0 { T_V0, T_A00, T_A10, T_A20, T_IL00, T_IL10, T_IL20, T_IV0, NT0 };  // T_IV0 = 1 / T_V0
 enum Tab1 { T_V1, T_A01, T_A11, T_A21, T_IL11, T_IL21, NT1 };
 enum Tab2 { T_V2, T_A02, T_A12, T_A22, T_IL22, NT2 };
 

@@ -42,7 +42,7 @@ typedef enum {
 
 typedef enum { STS_SPHERICAL = 0, STS_CARTESIAN = 1 } sts_coord;
 typedef enum { STS_BC_ZEROFLUX = 0, STS_BC_DIRICHLET = 1, STS_BC_PERIODIC = 2 } sts_bc;
-typedef enum { STS_PC_JACOBI = 0, STS_PC_BLOCK_ILU0 = 1 } sts_pc;
+typedef enum { STS_PC_JACOBI = 0, STS_PC_BLOCK_ILU0 = 1, STS_PC_FACTOR = 2 } sts_pc;
 
 /* sts_create - a context for one grid and one operator.
  * Grid (Sec. 4.2 and Table "tab:grid" of the paper: a logically rectangular,
@@ -189,16 +189,42 @@ sts_status rkl2_step_nonlinear(sts_ctx *ctx, double *u, double dt, double kappa0
  * BE_linsolve) written as (V - dt S) u^{n+1} = V u^n + dt g and solved by the
  * PCG of Fig. "pcg" (Sec. 2.2).  u_n: u^n (read only).  x: on entry the
  * initial guess (pass a copy of u^n for the paper's x0 = u^n), on return the
- * solution; x must not alias u_n.  pc: STS_PC_JACOBI (PC1: diagonal) or
+ * solution; x must not alias u_n.  pc: STS_PC_JACOBI (PC1: diagonal),
  * STS_PC_BLOCK_ILU0 (PC2: zero-fill ILU on non-overlapping blocks of
  * block[3] cells, each <= 8, couplings across blocks dropped; Sec. 2.3,
- * Appendix A).  Stops when ||b - A x_k||_2 <= rtol ||b||_2 (recursively
+ * Appendix A) or STS_PC_FACTOR (M^-1 = G G^T with the context's factor G:
+ * sts_set_pc_factor or cnn_pc_factor; not in the paper).  Stops when ||b - A x_k||_2 <= rtol ||b||_2 (recursively
  * updated residual) or after maxit iterations.  *iters and *relres (may be
  * NULL) receive the iteration count and the final relative residual.
  * Returns STS_NOT_CONVERGED at maxit and STS_BREAKDOWN if p.Ap <= 0 or a
  * pivot <= 0.  Synchronises the stream.  */
 sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, int pc,
                         const int block[3], double rtol, int maxit, int *iters, double *relres);
+
+/* The factored preconditioner M^-1 = G G^T (not in the paper: a third
+ * preconditioner for the PCG of Fig. "pcg" beside PC1 and PC2 of Sec. 2.3,
+ * whose factor a network can predict, cnn_pc_factor).  G is lower
+ * triangular in the cells' lexicographic order: row c holds G[c, c] and
+ * G[c, c - e_a] for the -1 neighbours along axes a = 0, 1, 2 that lie in the
+ * grid (no wrap across a periodic axis); with a positive diagonal G is
+ * nonsingular and M^-1 symmetric positive definite.  Layout: device FP32
+ * g[4][n0][n1][n2], g[0] = G[c, c], g[1 + a] = G[c, c - e_a] (entries whose
+ * neighbour does not exist are ignored).  */
+
+/* sts_set_pc_factor - copies g into the context (used by be_pcg_solve with
+ * STS_PC_FACTOR until the next call).  STS_EINVAL if a diagonal entry is not
+ * finite and positive or another entry is not finite.  Synchronises.  */
+sts_status sts_set_pc_factor(sts_ctx *ctx, const float *g);
+/* sts_apply_pc_factor - z = G (G^T r) with the context's factor; r, z device
+ * FP64 [n0][n1][n2], not overlapping.  */
+sts_status sts_apply_pc_factor(sts_ctx *ctx, const double *r, double *z);
+/* sts_pc_objective - the factor's training objective for a probe vector z
+ * (device FP64): L = ||G^T A G z - z||_2^2 / N with A = V - dt S of the
+ * context's operator (N cells), into *loss (HOST), and, if dg != NULL, its
+ * gradient dL/dG[c, m] = 2 (y_c r_m + s_c z_m) / N (w = G z, y = A w,
+ * r = G^T y - z, s = A G r) in the layout of g as device FP64 [4][cells]
+ * (zero where the entry does not exist).  Synchronises.  */
+sts_status sts_pc_objective(sts_ctx *ctx, double dt, const double *z, double *loss, double *dg);
 
 /* Resistive diffusion of the vector potential, dA/dt = -eta curl curl A
  * (Eq. mhd:a, boxed; eta stands for c^2 eta / 4 pi, constant as in the
@@ -319,6 +345,8 @@ sts_status cnn_pack_input(sts_cnn *net, const double *F_prev, double dt, const d
  *           mask16 NULL: no mask
  *   kind 3: out = FP32 [cells][16], conv + bias
  *   kind 4: out = FP32 [cells][16], adjoint convolution, no mask
+ *   kind 5: out = FP32 [cells][4],  channels 0..3 of conv + bias (output
+ *           layer of the factor network)
  * in16 and out must not overlap.  */
 sts_status cnn_conv(sts_cnn *net, int layer, int kind, const void *in16, const void *mask16,
                     void *out);
@@ -372,6 +400,49 @@ sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const d
  * Synchronises the stream.  */
 sts_status cnn_guess(sts_cnn *net, const double *T_prev, double dt, double *x0, int *used_net,
                      double relres[2]);
+
+/* The factor network: a network of the same architecture whose last layer
+ * has 4 output channels o = (o0, o1, o2, o3) per cell, which give the factor
+ * of the STS_PC_FACTOR preconditioner M^-1 = G G^T (see sts_set_pc_factor):
+ *   G[c, c] = d_c exp(o0_c),  G[c, c - e_a] = d_c o_(1+a),c,  d_c = A_cc^-1/2,
+ * with A = V - dt S the backward-Euler matrix of the context's operator, so
+ * that M^-1 is symmetric positive definite for any outputs and point Jacobi
+ * for o = 0 (not in the paper: a learned alternative to PC1 / PC2 of
+ * Sec. 2.3).  Its input features (bf16 [cells][16]) are
+ *   x[c][0] = log(A_cc / V_c) / log(1 + dt / dt_E),
+ *   x[c][1] = (T[c] - T_shift) T_scale, others 0.
+ * cnn_num_params, cnn_set_weights, cnn_get_weights, cnn_conv,
+ * cnn_weight_grad, cnn_set_adam, cnn_adam_step and cnn_destroy apply as for
+ * the initial-guess network (the last layer has 4 output channels);
+ * cnn_pack_input, cnn_forward, cnn_train_step and cnn_guess reject it.  */
+sts_status cnn_create_pc(sts_cnn **out, sts_ctx *ctx, int layers, int channels);
+/* cnn_pc_set_norm - the temperature scalings of the input features.  */
+sts_status cnn_pc_set_norm(sts_cnn *net, double T_shift, double T_scale);
+/* cnn_pc_factor - the network's factor for the context's current operator
+ * at dt, from the temperature T (device FP64), stored as the context's
+ * STS_PC_FACTOR factor.  Fallback: if an entry is not finite the context's
+ * factor becomes point Jacobi (o = 0) and *used_net (may be NULL) is 0.
+ * Synchronises.  */
+sts_status cnn_pc_factor(sts_cnn *net, const double *T, double dt, int *used_net);
+/* cnn_pc_grad - the gradient of the factor's objective for the probe vector
+ * z (device FP64, drawn by the caller) with respect to the network
+ * parameters, into grad (device FP32, layers x 6928 values in the padded
+ * layout of cnn_weight_grad), by back-propagation through the entry maps
+ * and the network: dL/do0 = dL/dG[c, c] G[c, c], dL/do_(1+a) =
+ * dL/dG[c, c - e_a] d_c.  Leaves the network's factor set in the context.
+ * *loss (may be NULL) receives L.  STS_BREAKDOWN if the factor has a
+ * non-finite entry.  */
+sts_status cnn_pc_grad(sts_cnn *net, const double *T, double dt, const double *z, float *grad,
+                       double *loss);
+/* cnn_pc_train_step - one Adam step (constants of cnn_set_adam, rate lr) on
+ * the factor's objective for the probe vector z (device FP64, drawn by the
+ * caller): L = ||G^T A G z - z||^2 / N at the context's operator and dt
+ * (see sts_pc_objective), with the gradient of cnn_pc_grad.  Leaves the
+ * step's factor (before the update) set in the context.  *loss (may be
+ * NULL) receives L before the step.  STS_BREAKDOWN if the factor has a
+ * non-finite entry (no update).  */
+sts_status cnn_pc_train_step(sts_cnn *net, const double *T, double dt, const double *z, float lr,
+                             double *loss);
 
 #ifdef __cplusplus
 }

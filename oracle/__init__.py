@@ -21,6 +21,8 @@ Modules
   nonlinear - conduction with kappa taken from the current state (no lagging)
   resistivity - edge-staggered curl curl A (Eq. mhd:a) and its BE + PC1 solve
   cnn       - FP64 reference of the small 3D CNN used for learned initial guesses
+  learned_pc - the learned factored preconditioner M^-1 = G G^T: its entries,
+              applications, training objective and gradient
 
 Parity status: every function is pinned by the CPU tests in
 tests/test_oracle_*.py (closed forms, invariants, brute force on tiny grids);

@@ -15,7 +15,7 @@ STS_OK, STS_NOT_CONVERGED = 0, 1
 STS_EINVAL, STS_EHIP, STS_ENOMEM, STS_BREAKDOWN = -1, -2, -3, -4
 SPHERICAL, CARTESIAN = 0, 1
 BC_ZEROFLUX, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
-PC_JACOBI, PC_BLOCK_ILU0 = 0, 1
+PC_JACOBI, PC_BLOCK_ILU0, PC_FACTOR = 0, 1, 2
 SHELL_BC = (BC_DIRICHLET, BC_ZEROFLUX, BC_ZEROFLUX, BC_ZEROFLUX, BC_PERIODIC, BC_PERIODIC)
 
 _STATUS = {0: "STS_OK", 1: "STS_NOT_CONVERGED", -1: "STS_EINVAL", -2: "STS_EHIP",
@@ -81,6 +81,14 @@ def load():
         "cnn_set_adam": (I, [P, D, D, D]),
         "cnn_adam_step": (I, [P, P, ctypes.c_float]),
         "cnn_guess": (I, [P, P, D, P, PI, PD]),
+        "sts_set_pc_factor": (I, [P, P]),
+        "sts_apply_pc_factor": (I, [P, P, P]),
+        "sts_pc_objective": (I, [P, D, P, PD, P]),
+        "cnn_create_pc": (I, [ctypes.POINTER(P), P, I, I]),
+        "cnn_pc_set_norm": (I, [P, D, D]),
+        "cnn_pc_factor": (I, [P, P, D, PI]),
+        "cnn_pc_train_step": (I, [P, P, D, P, ctypes.c_float, PD]),
+        "cnn_pc_grad": (I, [P, P, D, P, P, PD]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -100,7 +108,9 @@ def exported_symbols():
             "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
             "cnn_get_weights", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
             "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_set_adam", "cnn_adam_step",
-            "cnn_guess"]
+            "cnn_guess", "sts_set_pc_factor", "sts_apply_pc_factor", "sts_pc_objective",
+            "cnn_create_pc", "cnn_pc_set_norm", "cnn_pc_factor", "cnn_pc_train_step",
+            "cnn_pc_grad"]
 
 
 def _ptr(t: torch.Tensor | None, ncell: int, name: str, ncomp: int | None = 1,
@@ -317,6 +327,32 @@ class Context:
         self._check(st, (STS_OK, STS_NOT_CONVERGED) if allow_not_converged else (STS_OK,))
         return it.value, rel.value, st
 
+    def set_pc_factor(self, g):
+        """The STS_PC_FACTOR factor from a device FP32 tensor [4, n0, n1, n2]."""
+        self._sync_stream()
+        self._check(self._lib.sts_set_pc_factor(self._h, _ptr(g, self.ncell, "g", 4,
+                                                              dtype=torch.float32)))
+
+    def apply_pc_factor(self, r, out=None):
+        """z = G (G^T r) with the context's factor."""
+        self._sync_stream()
+        if out is None:
+            out = torch.empty_like(r)
+        self._check(self._lib.sts_apply_pc_factor(self._h, _ptr(r, self.ncell, "r"),
+                                                  _ptr(out, self.ncell, "out")))
+        return out
+
+    def pc_objective(self, dt, z, want_grad=True):
+        """(L, dL/dG as a device FP64 tensor [4, n0, n1, n2] or None)."""
+        self._sync_stream()
+        loss = ctypes.c_double()
+        dg = torch.empty((4,) + tuple(z.shape), dtype=torch.float64, device=z.device) \
+            if want_grad else None
+        self._check(self._lib.sts_pc_objective(self._h, float(dt), _ptr(z, self.ncell, "z"),
+                                               ctypes.byref(loss),
+                                               _ptr(dg, self.ncell, "dg", 4)))
+        return loss.value, dg
+
     def be_residual(self, u_n, x, dt) -> float:
         self._sync_stream()
         n = self.ncell
@@ -326,7 +362,7 @@ class Context:
         return rel.value
 
 
-CNN_RELU, CNN_LINEAR, CNN_INPUT_GRAD, CNN_F32, CNN_INPUT_GRAD_F32 = 0, 1, 2, 3, 4
+CNN_RELU, CNN_LINEAR, CNN_INPUT_GRAD, CNN_F32, CNN_INPUT_GRAD_F32, CNN_OUT4 = 0, 1, 2, 3, 4, 5
 CNN_PADDED_PARAMS = 16 * 16 * 27 + 16  # per layer, cnn_weight_grad's output
 
 
@@ -334,12 +370,15 @@ class Cnn:
     """Learned initial guess (sts_cnn): a 3D CNN on the context's grid.
     Activations are bfloat16 tensors of shape [cells, 16]."""
 
+    _create = "cnn_create"
+
     def __init__(self, ctx: Context, layers=4, channels=16):
         self.ctx = ctx
         self._lib = ctx._lib
         h = ctypes.c_void_p()
         ctx._sync_stream()
-        ctx._check(self._lib.cnn_create(ctypes.byref(h), ctx._h, int(layers), int(channels)))
+        ctx._check(getattr(self._lib, self._create)(ctypes.byref(h), ctx._h, int(layers),
+                                                    int(channels)))
         self._h = h
         self.layers = layers
         self.nparam = self._lib.cnn_num_params(h)
@@ -403,12 +442,16 @@ class Cnn:
                 out = torch.empty((n, 16), dtype=torch.bfloat16, device=x.device)
             elif kind == CNN_LINEAR:
                 out = torch.empty(n, dtype=torch.float32, device=x.device)
+            elif kind == CNN_OUT4:
+                out = torch.empty((n, 4), dtype=torch.float32, device=x.device)
             else:
                 out = torch.empty((n, 16), dtype=torch.float32, device=x.device)
         if kind in (CNN_RELU, CNN_INPUT_GRAD):
             po = self._act(out, "out")
         elif kind == CNN_LINEAR:
             po = _ptr(out, n, "out", 1, dtype=torch.float32)
+        elif kind == CNN_OUT4:
+            po = _ptr(out, n, "out", 4, dtype=torch.float32)
         else:
             po = _ptr(out, n, "out", 16, dtype=torch.float32)
         self._chk(self._lib.cnn_conv(self._h, int(layer), int(kind), self._act(x, "x"),
@@ -464,6 +507,47 @@ class Cnn:
         self._chk(self._lib.cnn_guess(self._h, _ptr(T_prev, n, "T_prev"), float(dt),
                                       _ptr(x0, n, "x0"), ctypes.byref(used), rel))
         return x0, bool(used.value), (rel[0], rel[1])
+
+
+class CnnPC(Cnn):
+    """The factor network (cnn_create_pc): 4 output channels giving the
+    factor G of the STS_PC_FACTOR preconditioner M^-1 = G G^T."""
+
+    _create = "cnn_create_pc"
+
+    def set_norm(self, T_shift, T_scale):
+        self._chk(self._lib.cnn_pc_set_norm(self._h, float(T_shift), float(T_scale)))
+
+    def factor(self, T, dt) -> bool:
+        """The network's factor for the context's operator at dt, set as the
+        context's factor; False if it fell back to point Jacobi."""
+        self.ctx._sync_stream()
+        used = ctypes.c_int()
+        self._chk(self._lib.cnn_pc_factor(self._h, _ptr(T, self.ctx.ncell, "T"), float(dt),
+                                          ctypes.byref(used)))
+        return bool(used.value)
+
+    def grad(self, T, dt, z, out=None):
+        """(loss, gradient as a device FP32 tensor of layers * 6928 values)."""
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        if out is None:
+            out = torch.empty(self.layers * CNN_PADDED_PARAMS, dtype=torch.float32,
+                              device=T.device)
+        loss = ctypes.c_double()
+        self._chk(self._lib.cnn_pc_grad(self._h, _ptr(T, n, "T"), float(dt), _ptr(z, n, "z"),
+                                        _ptr(out, self.layers * CNN_PADDED_PARAMS, "grad", 1,
+                                             dtype=torch.float32), ctypes.byref(loss)))
+        return loss.value, out
+
+    def train_step(self, T, dt, z, lr, want_loss=True):
+        self.ctx._sync_stream()
+        n = self.ctx.ncell
+        loss = ctypes.c_double()
+        self._chk(self._lib.cnn_pc_train_step(self._h, _ptr(T, n, "T"), float(dt),
+                                              _ptr(z, n, "z"), float(lr),
+                                              ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
 
 
 # Module-level names of the C ABI (same names, Python arguments).
@@ -535,6 +619,38 @@ def sts_be_residual(ctx: Context, u_n, x, dt) -> float:
 
 def cnn_create(ctx: Context, layers=4, channels=16) -> Cnn:
     return Cnn(ctx, layers, channels)
+
+
+def cnn_create_pc(ctx: Context, layers=4, channels=16) -> CnnPC:
+    return CnnPC(ctx, layers, channels)
+
+
+def cnn_pc_set_norm(net: CnnPC, T_shift, T_scale):
+    net.set_norm(T_shift, T_scale)
+
+
+def cnn_pc_factor(net: CnnPC, T, dt) -> bool:
+    return net.factor(T, dt)
+
+
+def cnn_pc_train_step(net: CnnPC, T, dt, z, lr, want_loss=True):
+    return net.train_step(T, dt, z, lr, want_loss)
+
+
+def cnn_pc_grad(net: CnnPC, T, dt, z, out=None):
+    return net.grad(T, dt, z, out)
+
+
+def sts_set_pc_factor(ctx: Context, g):
+    ctx.set_pc_factor(g)
+
+
+def sts_apply_pc_factor(ctx: Context, r, out=None):
+    return ctx.apply_pc_factor(r, out)
+
+
+def sts_pc_objective(ctx: Context, dt, z, want_grad=True):
+    return ctx.pc_objective(dt, z, want_grad)
 
 
 def cnn_destroy(net: Cnn):

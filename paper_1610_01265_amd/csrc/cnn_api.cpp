@@ -31,7 +31,7 @@ namespace {
 #define NLAUNCHCHK() NHIPCHK(hipGetLastError())
 
 int in_ch(const sts_cnn *net, int l) { return l == 0 ? 2 : kCnnC; }
-int out_ch(const sts_cnn *net, int l) { return l == net->layers - 1 ? 1 : kCnnC; }
+int out_ch(const sts_cnn *net, int l) { return l == net->layers - 1 ? net->nout : kCnnC; }
 
 long long count_params(const sts_cnn *net) {
   long long n = 0;
@@ -63,16 +63,46 @@ void refresh_frags(sts_cnn *net) {
 
 const float *bias(const sts_cnn *net, int l) { return net->d_P + (size_t)l * kCnnPPerLayer + kCnnWPerLayer; }
 
-// network input into act(0), forward through every layer into d_pred
-void forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev) {
+void adam(sts_cnn *net, const float *G, float lr);
+
+// forward from the packed input act(0) through every layer into d_pred
+// (one channel: kind 1; the factor network's four channels: kind 5)
+void forward_packed(sts_cnn *net) {
   const CnnLaunch L = net->launch();
-  launch_cnn_pack_input(L, F_prev, T_prev, dt * net->rhs_scale, net->t_shift, net->t_scale,
-                        net->act(0));
   for (int l = 0; l + 1 < net->layers; ++l)
     launch_cnn_conv(L, 0, net->act(l), net->frag(l, 0), bias(net, l), nullptr, net->act(l + 1),
                     nullptr);
   const int l = net->layers - 1;
-  launch_cnn_conv(L, 1, net->act(l), net->frag(l, 0), bias(net, l), nullptr, nullptr, net->d_pred);
+  launch_cnn_conv(L, net->nout == 1 ? 1 : 5, net->act(l), net->frag(l, 0), bias(net, l), nullptr,
+                  nullptr, net->d_pred);
+}
+
+// network input into act(0), forward through every layer into d_pred
+void forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev) {
+  launch_cnn_pack_input(net->launch(), F_prev, T_prev, dt * net->rhs_scale, net->t_shift,
+                        net->t_scale, net->act(0));
+  forward_packed(net);
+}
+
+// gradient of the loss with respect to the network output in g(0):
+// back-propagation into grad (padded layout, layers x kCnnPPerLayer)
+void backward(sts_cnn *net, float *grad) {
+  const CnnLaunch L = net->launch();
+  int q = 0;  // g(q): gradient with respect to the output of layer l
+  for (int l = net->layers - 1; l >= 0; --l) {
+    float *G = grad + (size_t)l * kCnnPPerLayer;
+    launch_cnn_wgrad(L, net->act(l), net->g(q), net->d_wpart, G);
+    if (l > 0) {
+      launch_cnn_conv(L, 2, net->g(q), net->frag(l, 1), nullptr, net->act(l), net->g(1 - q),
+                      nullptr);
+      q = 1 - q;
+    }
+  }
+}
+
+void backward_adam(sts_cnn *net, float lr) {
+  backward(net, net->d_G);
+  adam(net, net->d_G, lr);
 }
 
 bool finite_nonzero(double x) { return std::isfinite(x) && x != 0.0; }
@@ -90,7 +120,7 @@ void adam(sts_cnn *net, const float *G, float lr) {
 
 extern "C" {
 
-sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
+static sts_status create_net(sts_cnn **out, sts_ctx *ctx, int layers, int channels, int nout) {
   if (!out || !ctx) return STS_EINVAL;
   *out = nullptr;
   if (layers < 2 || layers > 8) {
@@ -104,6 +134,7 @@ sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
   sts_cnn *net = new sts_cnn;
   net->ctx = ctx;
   net->layers = layers;
+  net->nout = nout;
   net->ncell = ctx->ncell;
   net->nparam = count_params(net);
   const size_t np = (size_t)layers * kCnnPPerLayer, nc = (size_t)ctx->ncell;
@@ -119,7 +150,7 @@ sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
   A(&net->d_frag, (size_t)2 * layers * kCnnFrag * 2);
   A(&net->d_act, (size_t)layers * nc * kCnnC * 2);
   A(&net->d_g, (size_t)2 * nc * kCnnC * 2);
-  A((void **)&net->d_pred, nc * 4);
+  A((void **)&net->d_pred, nc * 4 * nout);
   A((void **)&net->d_F, nc * 8);
   A((void **)&net->d_wpart, (size_t)cnn_wgrad_parts() * (kCnnTaps + 1) * 256 * 4);
   const int npart = std::max(cnn_loss_parts(), 2 * cnn_moment_parts());
@@ -157,6 +188,14 @@ sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
   }
   *out = net;
   return STS_OK;
+}
+
+sts_status cnn_create(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
+  return create_net(out, ctx, layers, channels, 1);
+}
+
+sts_status cnn_create_pc(sts_cnn **out, sts_ctx *ctx, int layers, int channels) {
+  return create_net(out, ctx, layers, channels, 4);
 }
 
 sts_status cnn_destroy(sts_cnn *net) {
@@ -289,8 +328,11 @@ sts_status cnn_conv(sts_cnn *net, int layer, int kind, const void *in16, const v
     case 4:
       launch_cnn_conv(L, 3, in16, net->frag(layer, 1), nullptr, nullptr, nullptr, (float *)out);
       break;
+    case 5:
+      launch_cnn_conv(L, 5, in16, net->frag(layer, 0), b, nullptr, nullptr, (float *)out);
+      break;
     default:
-      NFAIL(STS_EINVAL, "cnn_conv: kind must be 0..4");
+      NFAIL(STS_EINVAL, "cnn_conv: kind must be 0..5");
   }
   NLAUNCHCHK();
   return STS_OK;
@@ -310,6 +352,7 @@ sts_status cnn_weight_grad(sts_cnn *net, int layer, const void *act16, const voi
 sts_status cnn_forward(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
                        double *x0) {
   if (!net) return STS_EINVAL;
+  if (net->nout != 1) NFAIL(STS_EINVAL, "cnn_forward: not an initial-guess network");
   if (!F_prev || !T_prev || !x0) NFAIL(STS_EINVAL, "cnn_forward: null array");
   if (!std::isfinite(dt)) NFAIL(STS_EINVAL, "cnn_forward: dt must be finite");
   forward(net, F_prev, dt, T_prev);
@@ -321,6 +364,7 @@ sts_status cnn_forward(sts_cnn *net, const double *F_prev, double dt, const doub
 sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const double *T_prev,
                           const double *x_star, float lr, double *loss) {
   if (!net) return STS_EINVAL;
+  if (net->nout != 1) NFAIL(STS_EINVAL, "cnn_train_step: not an initial-guess network");
   if (!F_prev || !T_prev || !x_star) NFAIL(STS_EINVAL, "cnn_train_step: null array");
   if (!std::isfinite(dt)) NFAIL(STS_EINVAL, "cnn_train_step: dt must be finite");
   if (!(lr > 0.0f) || !std::isfinite(lr)) NFAIL(STS_EINVAL, "cnn_train_step: lr must be > 0");
@@ -328,17 +372,7 @@ sts_status cnn_train_step(sts_cnn *net, const double *F_prev, double dt, const d
   forward(net, F_prev, dt, T_prev);
   launch_cnn_loss(L, net->d_pred, x_star, T_prev, 1.0 / net->delta_scale, net->g(0), net->d_part);
   if (loss) launch_cnn_sum_parts(L, net->d_part, cnn_loss_parts(), net->d_out);
-  int q = 0;  // g(q): gradient with respect to the output of layer l
-  for (int l = net->layers - 1; l >= 0; --l) {
-    float *G = net->d_G + (size_t)l * kCnnPPerLayer;
-    launch_cnn_wgrad(L, net->act(l), net->g(q), net->d_wpart, G);
-    if (l > 0) {
-      launch_cnn_conv(L, 2, net->g(q), net->frag(l, 1), nullptr, net->act(l), net->g(1 - q),
-                      nullptr);
-      q = 1 - q;
-    }
-  }
-  adam(net, net->d_G, lr);
+  backward_adam(net, lr);
   NLAUNCHCHK();
   if (loss) {
     double h;
@@ -373,6 +407,7 @@ sts_status cnn_guess(sts_cnn *net, const double *T_prev, double dt, double *x0, 
                      double relres[2]) {
   if (!net) return STS_EINVAL;
   sts_ctx *ctx = net->ctx;
+  if (net->nout != 1) NFAIL(STS_EINVAL, "cnn_guess: not an initial-guess network");
   if (!T_prev || !x0 || T_prev == x0) NFAIL(STS_EINVAL, "cnn_guess: null or aliased arrays");
   if (!(dt > 0.0) || !std::isfinite(dt)) NFAIL(STS_EINVAL, "cnn_guess: dt must be finite, > 0");
   sts_status st = apply_F(ctx, T_prev, net->d_F, 1);
@@ -394,6 +429,101 @@ sts_status cnn_guess(sts_cnn *net, const double *T_prev, double dt, double *x0, 
     relres[1] = r_prev;
   }
   return STS_OK;
+}
+
+// ---- the factor network: M^-1 = G G^T for STS_PC_FACTOR -----------------
+
+// input features of the factor network at dt into act(0)
+static sts_status pc_features(sts_cnn *net, const double *T, double dt) {
+  sts_ctx *ctx = net->ctx;
+  double dte;
+  sts_status st = sts_dt_euler(ctx, &dte);
+  if (st) return st;
+  const double lscale = 1.0 / std::log1p(dt / dte);
+  launch_pc_pack(ctx, dt, lscale, T, net->t_shift, net->t_scale, net->act(0));
+  return STS_OK;
+}
+
+static sts_status pc_checks(sts_cnn *net, const char *name, const double *T, double dt) {
+  sts_ctx *ctx = net->ctx;
+  if (net->nout != 4) NFAIL(STS_EINVAL, std::string(name) + ": not a factor network");
+  if (ctx->op == OP_NONE) NFAIL(STS_EINVAL, "no operator set");
+  if (ctx->prec != 0) NFAIL(STS_EINVAL, std::string(name) + ": FP64 operators only");
+  if (!T) NFAIL(STS_EINVAL, std::string(name) + ": null T");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    NFAIL(STS_EINVAL, std::string(name) + ": dt must be finite, > 0");
+  return STS_OK;
+}
+
+sts_status cnn_pc_set_norm(sts_cnn *net, double T_shift, double T_scale) {
+  if (!net) return STS_EINVAL;
+  if (!std::isfinite(T_shift) || !finite_nonzero(T_scale))
+    NFAIL(STS_EINVAL, "cnn_pc_set_norm: scalings must be finite, T_scale nonzero");
+  net->t_shift = T_shift;
+  net->t_scale = T_scale;
+  return STS_OK;
+}
+
+sts_status cnn_pc_factor(sts_cnn *net, const double *T, double dt, int *used_net) {
+  if (!net) return STS_EINVAL;
+  sts_status st = pc_checks(net, "cnn_pc_factor", T, dt);
+  if (st) return st;
+  if ((st = pc_features(net, T, dt))) return st;
+  forward_packed(net);
+  NLAUNCHCHK();
+  st = build_pc_factor(net->ctx, dt, net->d_pred);
+  bool used = st == STS_OK;
+  if (st == STS_BREAKDOWN) st = build_pc_factor(net->ctx, dt, nullptr);  // point Jacobi
+  if (st) return st;
+  if (used_net) *used_net = used ? 1 : 0;
+  return STS_OK;
+}
+
+// features, forward, factor, objective sweeps with the output gradient in
+// g(0), back-propagation into grad; the loss partial sum into d_out[0]
+static sts_status pc_gradient(sts_cnn *net, const char *name, const double *T, double dt,
+                              const double *z, float *grad, bool want_loss) {
+  sts_status st = pc_checks(net, name, T, dt);
+  if (st) return st;
+  if (!z) NFAIL(STS_EINVAL, std::string(name) + ": null z");
+  sts_ctx *ctx = net->ctx;
+  if ((st = pc_features(net, T, dt))) return st;
+  forward_packed(net);
+  NLAUNCHCHK();
+  if ((st = build_pc_factor(ctx, dt, net->d_pred))) return st;
+  if ((st = pc_objective_sweeps(ctx, dt, z, nullptr, net->g(0)))) return st;
+  if (want_loss) launch_cnn_sum_parts(net->launch(), ctx->d_red, pc_parts(ctx), net->d_out);
+  backward(net, grad);
+  NLAUNCHCHK();
+  return STS_OK;
+}
+
+static sts_status read_loss(sts_cnn *net, double *loss) {
+  double h;
+  NHIPCHK(hipMemcpyAsync(&h, net->d_out, 8, hipMemcpyDeviceToHost, net->ctx->stream));
+  NHIPCHK(hipStreamSynchronize(net->ctx->stream));
+  *loss = h / (double)net->ncell;
+  return STS_OK;
+}
+
+sts_status cnn_pc_grad(sts_cnn *net, const double *T, double dt, const double *z, float *grad,
+                       double *loss) {
+  if (!net) return STS_EINVAL;
+  if (!grad) NFAIL(STS_EINVAL, "cnn_pc_grad: null gradient array");
+  sts_status st = pc_gradient(net, "cnn_pc_grad", T, dt, z, grad, loss != nullptr);
+  if (st) return st;
+  return loss ? read_loss(net, loss) : STS_OK;
+}
+
+sts_status cnn_pc_train_step(sts_cnn *net, const double *T, double dt, const double *z, float lr,
+                             double *loss) {
+  if (!net) return STS_EINVAL;
+  if (!(lr > 0.0f) || !std::isfinite(lr)) NFAIL(STS_EINVAL, "cnn_pc_train_step: lr must be > 0");
+  sts_status st = pc_gradient(net, "cnn_pc_train_step", T, dt, z, net->d_G, loss != nullptr);
+  if (st) return st;
+  adam(net, net->d_G, lr);
+  NLAUNCHCHK();
+  return loss ? read_loss(net, loss) : STS_OK;
 }
 
 }  // extern "C"

@@ -21,7 +21,8 @@ struct CnnLaunch {
 };
 
 // kind: 0 ReLU -> bf16 [cells][16]; 1 channel 0 -> FP32 [cells];
-// 2 masked (mask > 0) -> bf16 [cells][16]; 3 -> FP32 [cells][16]
+// 2 masked (mask > 0) -> bf16 [cells][16]; 3 -> FP32 [cells][16];
+// 5 channels 0..3 -> FP32 [cells][4]
 void launch_cnn_conv(const CnnLaunch &L, int kind, const void *in, const void *wfrag,
                      const float *bias, const void *mask, void *out_bf, float *outf);
 int cnn_wgrad_parts();
@@ -48,6 +49,7 @@ void launch_cnn_sum_parts(const CnnLaunch &L, const double *part, int n, double 
 struct sts_cnn {
   sts_ctx *ctx = nullptr;
   int layers = 0;
+  int nout = 1;                // output channels: 1 (initial guess) or 4 (factor network)
   long long ncell = 0;
   long long nparam = 0;        // unpadded parameter count (host weight vector)
   float *d_P = nullptr;        // padded FP32 master parameters, layers * kCnnPPerLayer
@@ -57,7 +59,7 @@ struct sts_cnn {
   void *d_frag = nullptr;      // bf16 fragments: layer l forward at 2l, transposed at 2l+1
   void *d_act = nullptr;       // bf16 [layers][cells][16]: network input, hidden activations
   void *d_g = nullptr;         // bf16 [2][cells][16]: back-propagated gradients
-  float *d_pred = nullptr;     // FP32 [cells] network output
+  float *d_pred = nullptr;     // FP32 [cells][nout] network output
   double *d_F = nullptr;       // FP64 [cells] F(T_prev) for cnn_guess
   float *d_wpart = nullptr;    // weight-gradient partials
   double *d_part = nullptr;    // loss / moment partials

@@ -38,7 +38,7 @@ constexpr int HKC = TKC + 2, HJC = TJC + 2;
 constexpr int PLC = HKC * HJC;   // cells per LDS plane (tile + halo)
 
 // epilogues of k_conv (numbers are the cnn_conv kinds of the C ABI)
-enum { CV_RELU = 0, CV_LAST = 1, CV_MASK = 2, CV_F32 = 3 };
+enum { CV_RELU = 0, CV_LAST = 1, CV_MASK = 2, CV_F32 = 3, CV_OUT4 = 5 };
 
 // target number of workgroups of the plane-marching kernels, and the output
 // planes the convolution computes per iteration (between two waits for
@@ -64,6 +64,7 @@ __device__ __forceinline__ int tap_c(int t) { return t % 3 - 1; }
 //   mode CV_LAST: outf[cell] = acc(co 0) + bias[0]     (FP32, one channel)
 //   mode CV_MASK: out_bf = bf16(acc * (mask[cell][co] > 0))   (no mask: acc)
 //   mode CV_F32 : outf[cell][co] = acc + bias           (FP32; bias optional)
+//   mode CV_OUT4: outf[cell][co] = acc + bias, co < 4   (FP32, four channels)
 template <int MODE>
 __global__ void __launch_bounds__(256)
     k_conv(CnnGrid g, const __bf16 *__restrict__ in, const __bf16 *__restrict__ wfrag,
@@ -155,6 +156,11 @@ __global__ void __launch_bounds__(256)
         const int co0 = 4 * grp;
         if (MODE == CV_LAST) {
           if (grp == 0) outf[cell] = acc[nb][0] + bias[0];
+        } else if (MODE == CV_OUT4) {
+          if (grp == 0)
+            *reinterpret_cast<float4 *>(outf + cell * 4) =
+                make_float4(acc[nb][0] + bias[0], acc[nb][1] + bias[1], acc[nb][2] + bias[2],
+                            acc[nb][3] + bias[3]);
         } else if (MODE == CV_F32) {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
@@ -485,6 +491,9 @@ void launch_cnn_conv(const CnnLaunch &L, int mode, const void *in, const void *w
       break;
     case CV_MASK:
       hipLaunchKernelGGL(k_conv<CV_MASK>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      break;
+    case CV_OUT4:
+      hipLaunchKernelGGL(k_conv<CV_OUT4>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
       break;
     default:
       hipLaunchKernelGGL(k_conv<CV_F32>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);

@@ -1,0 +1,289 @@
+// The factored preconditioner M^-1 = G G^T of the backward-Euler PCG, with G
+// lower triangular in the cells' lexicographic order (r slowest, phi
+// fastest): row c holds the cell and its -1 neighbours c - e_a that lie in
+// the grid without wrapping across the periodic phi seam.  Entries are FP32
+// arrays g[q][cell]: g[0] = G[c, c], g[1 + a] = G[c, c - e_a] (ignored where
+// that neighbour does not exist); vectors and arithmetic are FP64.
+//
+//   (G^T x)_c = g0_c x_c + sum_a g_(1+a)(c + e_a) x_(c + e_a)
+//   (G x)_c   = g0_c x_c + sum_a g_(1+a)(c) x_(c - e_a)
+//
+// A learned factor comes from the network outputs o (4 per cell) and the
+// diagonal of A = V - dt S:  G[c, c] = d exp(o0), G[c, c - e_a] = d o_(1+a),
+// d = A_cc^-1/2, so M^-1 is symmetric positive definite for any outputs and
+// point Jacobi at o = 0.  The training objective per probe vector z is
+// L = ||G^T A G z - z||^2 / N; with w = G z, y = A w, r = G^T y - z,
+// q = G r, s = A q:  dL/dG[c, m] = 2 (y_c r_m + s_c z_m) / N.
+//
+// The kernels march the grid in 64 (phi) x 4 (theta) tiles of one r-plane,
+// workgroups striding over the tiles; neighbour values are plain loads
+// (the previous and next planes of the tile are in the caches).
+#include "cnn_internal.h"
+#include "k_common.h"
+#include "k_reduce.h"
+
+namespace sts {
+
+namespace {
+
+constexpr int TX = 64, TY = 4, NT = TX * TY;
+
+struct PcDims {
+  int n0, n1, n2;
+  long long n12, n;
+  int ntx, nty;
+  long long items;
+};
+
+PcDims dims_of(const sts_ctx *c) {
+  PcDims d;
+  d.n0 = c->n0;
+  d.n1 = c->n1;
+  d.n2 = c->n2;
+  d.n12 = (long long)c->n1 * c->n2;
+  d.n = c->ncell;
+  d.ntx = (c->n2 + TX - 1) / TX;
+  d.nty = (c->n1 + TY - 1) / TY;
+  d.items = (long long)d.ntx * d.nty * c->n0;
+  return d;
+}
+
+// Visit every cell once: workgroups stride over (tile, plane) items.
+template <class F>
+__device__ __forceinline__ void for_cells(const PcDims &d, F &&f) {
+  for (long long it = blockIdx.x; it < d.items; it += gridDim.x) {
+    const int bx = (int)(it % d.ntx);
+    const long long r = it / d.ntx;
+    const int by = (int)(r % d.nty);
+    const int i = (int)(r / d.nty);
+    const int k = bx * TX + threadIdx.x, j = by * TY + threadIdx.y;
+    if (k < d.n2 && j < d.n1) f(i, j, k, (long long)i * d.n12 + (long long)j * d.n2 + k);
+  }
+}
+
+// t = G^T x (- sub)
+__global__ void __launch_bounds__(NT)
+    k_pc_gt(PcDims d, const float *__restrict__ g, const double *__restrict__ x,
+            const double *__restrict__ sub, double *__restrict__ t, const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  const float *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
+  for_cells(d, [&](int i, int j, int k, long long c) {
+    double v = (double)g[c] * x[c];
+    if (i + 1 < d.n0) v += (double)g1[c + d.n12] * x[c + d.n12];
+    if (j + 1 < d.n1) v += (double)g2[c + d.n2] * x[c + d.n2];
+    if (k + 1 < d.n2) v += (double)g3[c + 1] * x[c + 1];
+    t[c] = sub ? v - sub[c] : v;
+  });
+}
+
+// z = G t; DOTS: partial sums r.z (region 0) and r.r (region cap)
+template <bool DOTS>
+__global__ void __launch_bounds__(NT)
+    k_pc_g(PcDims d, const float *__restrict__ g, const double *__restrict__ t,
+           double *__restrict__ z, const double *__restrict__ r, double *part, long long cap,
+           const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  const float *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
+  double rz = 0.0, rr = 0.0;
+  for_cells(d, [&](int i, int j, int k, long long c) {
+    double v = (double)g[c] * t[c];
+    if (i > 0) v += (double)g1[c] * t[c - d.n12];
+    if (j > 0) v += (double)g2[c] * t[c - d.n2];
+    if (k > 0) v += (double)g3[c] * t[c - 1];
+    z[c] = v;
+    if (DOTS) {
+      const double rv = r[c];
+      rz += rv * v;
+      rr += rv * rv;
+    }
+  });
+  if (DOTS)
+    wg_sum2<NT>(rz, rr, threadIdx.y * TX + threadIdx.x, part + blockIdx.x,
+                part + cap + blockIdx.x);
+}
+
+// 1 / sqrt(A_cc), A_cc = V - dt S_cc
+__device__ __forceinline__ double inv_sqrt_diag(const Grid &gr, const double *sdiag, double dt,
+                                                int i, int j, int k, long long c) {
+  return 1.0 / sqrt(vol(gr, i, j, k) - dt * sdiag[c]);
+}
+
+// Factor from the network outputs o4[cell][4] (null: o = 0, point Jacobi).
+// A non-finite entry sets *bad.
+__global__ void __launch_bounds__(NT)
+    k_pc_build(PcDims d, Grid gr, const double *__restrict__ sdiag, double dt,
+               const float *__restrict__ o4, float *__restrict__ g, int *bad) {
+  for_cells(d, [&](int i, int j, int k, long long c) {
+    const double dd = inv_sqrt_diag(gr, sdiag, dt, i, j, k, c);
+    double o[4] = {0.0, 0.0, 0.0, 0.0};
+    if (o4) {
+      const float4 v = *reinterpret_cast<const float4 *>(o4 + 4 * c);
+      o[0] = v.x;
+      o[1] = v.y;
+      o[2] = v.z;
+      o[3] = v.w;
+    }
+    const float e0 = (float)(dd * exp(o[0]));
+    const float e1 = i > 0 ? (float)(dd * o[1]) : 0.0f;
+    const float e2 = j > 0 ? (float)(dd * o[2]) : 0.0f;
+    const float e3 = k > 0 ? (float)(dd * o[3]) : 0.0f;
+    if (!(isfinite(e0) && e0 > 0.0f && isfinite(e1) && isfinite(e2) && isfinite(e3)))
+      atomicOr(bad, 1);
+    g[c] = e0;
+    g[c + d.n] = e1;
+    g[c + 2 * d.n] = e2;
+    g[c + 3 * d.n] = e3;
+  });
+}
+
+// A caller's factor: the diagonal must be finite and positive, the other
+// entries finite.
+__global__ void __launch_bounds__(NT)
+    k_pc_check(PcDims d, const float *__restrict__ g, int *bad) {
+  for_cells(d, [&](int i, int j, int k, long long c) {
+    const float e0 = g[c], e1 = g[c + d.n], e2 = g[c + 2 * d.n], e3 = g[c + 3 * d.n];
+    if (!(isfinite(e0) && e0 > 0.0f && isfinite(e1) && isfinite(e2) && isfinite(e3)))
+      atomicOr(bad, 1);
+  });
+}
+
+// Network input of the factor network, bf16 [cells][16]: channel 0 =
+// log(A_cc / V_c) * lscale, channel 1 = (T - tsh) * tsc, the rest 0.
+__global__ void __launch_bounds__(NT)
+    k_pc_pack(PcDims d, Grid gr, const double *__restrict__ sdiag, double dt, double lscale,
+              const double *__restrict__ T, double tsh, double tsc, __bf16 *__restrict__ x) {
+  for_cells(d, [&](int i, int j, int k, long long c) {
+    const double V = vol(gr, i, j, k);
+    const float f0 = (float)(log((V - dt * sdiag[c]) / V) * lscale);
+    const float f1 = (float)((T[c] - tsh) * tsc);
+    __bf16 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = (__bf16)0.0f;
+    v[0] = (__bf16)f0;
+    v[1] = (__bf16)f1;
+    uint4 lo, hi;
+    __builtin_memcpy(&lo, v, 16);
+    __builtin_memcpy(&hi, v + 8, 16);
+    uint4 *dst = reinterpret_cast<uint4 *>(x + 16 * c);
+    dst[0] = lo;
+    dst[1] = hi;
+  });
+}
+
+// Gradient of the objective: dg[q][cell] = dL/dG entries (FP64, may be
+// null); dout (bf16 [cells][16], may be null) = dL/do through the entry maps
+// (dg0 G_cc, dg_(1+a) d), channels 4..15 zero; partial sums of r.r.
+__global__ void __launch_bounds__(NT)
+    k_pc_grad(PcDims d, Grid gr, const double *__restrict__ sdiag, double dt,
+              const float *__restrict__ g, const double *__restrict__ y,
+              const double *__restrict__ r, const double *__restrict__ s,
+              const double *__restrict__ z, double *__restrict__ dg, __bf16 *__restrict__ dout,
+              double *part) {
+  const double two_n = 2.0 / (double)d.n;
+  double rr = 0.0;
+  for_cells(d, [&](int i, int j, int k, long long c) {
+    const double yc = y[c], sc_ = s[c], rc = r[c];
+    rr += rc * rc;
+    double e[4];
+    e[0] = two_n * (yc * rc + sc_ * z[c]);
+    e[1] = i > 0 ? two_n * (yc * r[c - d.n12] + sc_ * z[c - d.n12]) : 0.0;
+    e[2] = j > 0 ? two_n * (yc * r[c - d.n2] + sc_ * z[c - d.n2]) : 0.0;
+    e[3] = k > 0 ? two_n * (yc * r[c - 1] + sc_ * z[c - 1]) : 0.0;
+    if (dg) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dg[c + q * d.n] = e[q];
+    }
+    if (dout) {
+      const double dd = inv_sqrt_diag(gr, sdiag, dt, i, j, k, c);
+      __bf16 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = (__bf16)0.0f;
+      v[0] = (__bf16)(float)(e[0] * (double)g[c]);
+      v[1] = (__bf16)(float)(e[1] * dd);
+      v[2] = (__bf16)(float)(e[2] * dd);
+      v[3] = (__bf16)(float)(e[3] * dd);
+      uint4 lo, hi;
+      __builtin_memcpy(&lo, v, 16);
+      __builtin_memcpy(&hi, v + 8, 16);
+      uint4 *dst = reinterpret_cast<uint4 *>(dout + 16 * c);
+      dst[0] = lo;
+      dst[1] = hi;
+    }
+  });
+  wg_sum2<NT>(rr, 0.0, threadIdx.y * TX + threadIdx.x, part + blockIdx.x, nullptr);
+}
+
+// x += alpha p, r -= alpha y (alpha from the finalizer); no preconditioner
+// and no dots: those follow in k_pc_gt / k_pc_g<true>
+__global__ void __launch_bounds__(NT)
+    k_pass_b_xr(long long n, double *__restrict__ x, const double *__restrict__ p,
+                double *__restrict__ r, const double *__restrict__ y, const PcgScalars *sc) {
+  if (sc->done) return;
+  const double alpha = sc->alpha;
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long c = (long long)blockIdx.x * NT + threadIdx.y * TX + threadIdx.x; c < n;
+       c += stride) {
+    x[c] = x[c] + alpha * p[c];
+    r[c] = r[c] - alpha * y[c];
+  }
+}
+
+int grid_items(const PcDims &d) { return (int)(d.items < 2048 ? d.items : 2048); }
+
+}  // namespace
+
+int pc_parts(const sts_ctx *c) { return grid_items(dims_of(c)); }
+
+void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const double *sub,
+                  double *t, const PcgScalars *sc) {
+  const PcDims d = dims_of(c);
+  hipLaunchKernelGGL(k_pc_gt, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, x, sub, t,
+                     sc);
+}
+
+void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z, const double *r,
+                 double *part, const PcgScalars *sc) {
+  const PcDims d = dims_of(c);
+  if (r)
+    hipLaunchKernelGGL(k_pc_g<true>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, t,
+                       z, r, part, (long long)c->red_cap, sc);
+  else
+    hipLaunchKernelGGL(k_pc_g<false>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, t,
+                       z, nullptr, nullptr, 0LL, sc);
+}
+
+void launch_pc_build(const sts_ctx *c, double dt, const float *o4, float *g, int *bad) {
+  const PcDims d = dims_of(c);
+  hipLaunchKernelGGL(k_pc_build, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
+                     (const double *)c->d_sdiag, dt, o4, g, bad);
+}
+
+void launch_pc_check(const sts_ctx *c, const float *g, int *bad) {
+  const PcDims d = dims_of(c);
+  hipLaunchKernelGGL(k_pc_check, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, bad);
+}
+
+void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T, double tsh,
+                    double tsc, void *x) {
+  const PcDims d = dims_of(c);
+  hipLaunchKernelGGL(k_pc_pack, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
+                     (const double *)c->d_sdiag, dt, lscale, T, tsh, tsc, (__bf16 *)x);
+}
+
+void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y,
+                    const double *r, const double *s, const double *z, double *dg, void *dout,
+                    double *part) {
+  const PcDims d = dims_of(c);
+  hipLaunchKernelGGL(k_pc_grad, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
+                     (const double *)c->d_sdiag, dt, g, y, r, s, z, dg, (__bf16 *)dout, part);
+}
+
+void launch_pass_b_xr(const sts_ctx *c, double *x, const double *p, double *r, const double *y,
+                      const PcgScalars *sc) {
+  const long long n = c->ncell;
+  const long long nb = (n + NT - 1) / NT;
+  hipLaunchKernelGGL(k_pass_b_xr, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(TX, TY), 0,
+                     c->stream, n, x, p, r, y, sc);
+}
+
+}  // namespace sts

@@ -312,6 +312,10 @@ sts_status sts_destroy(sts_ctx *ctx) {
   dfree(ctx->d_red);
   dfree(ctx->d_sc);
   dfree(ctx->d_ilu);
+  dfree(ctx->d_gfac);
+  dfree(ctx->d_pct);
+  dfree(ctx->d_pcobj);
+  dfree(ctx->d_sc0);
   dfree(ctx->d_flag);
   dfree(ctx->d_tmp);
   dfree(ctx->d_rtab);
@@ -779,6 +783,10 @@ static sts_status pcg_workspace(sts_ctx *ctx, int pc, const int block[3], double
   if ((st = dalloc(ctx, (void **)&ctx->d_pcg, (size_t)7 * n * 8))) return st;
   int need = pcg_parts(ctx);
   if (pc == STS_PC_BLOCK_ILU0) need = std::max(need, ilu_parts(ctx, block));
+  if (pc == STS_PC_FACTOR) {
+    need = std::max(need, pc_parts(ctx));
+    if (!ctx->d_pct && (st = dalloc(ctx, (void **)&ctx->d_pct, (size_t)n * 8))) return st;
+  }
   if ((st = ensure_red(ctx, need))) return st;
   *fac = nullptr;
   if (pc == STS_PC_BLOCK_ILU0) {
@@ -904,7 +912,10 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "be_pcg_solve: dt must be finite, > 0");
   if (!(rtol >= 0.0) || !std::isfinite(rtol)) FAIL(STS_EINVAL, "be_pcg_solve: bad rtol");
   if (maxit < 0) FAIL(STS_EINVAL, "be_pcg_solve: maxit must be >= 0");
-  if (pc != STS_PC_JACOBI && pc != STS_PC_BLOCK_ILU0) FAIL(STS_EINVAL, "unknown preconditioner");
+  if (pc != STS_PC_JACOBI && pc != STS_PC_BLOCK_ILU0 && pc != STS_PC_FACTOR)
+    FAIL(STS_EINVAL, "unknown preconditioner");
+  if (pc == STS_PC_FACTOR && !ctx->gfac_set)
+    FAIL(STS_EINVAL, "STS_PC_FACTOR needs a factor (sts_set_pc_factor or cnn_pc_factor)");
   int blk[3] = {1, 1, 1};
   if (pc == STS_PC_BLOCK_ILU0) {
     if (!block) FAIL(STS_EINVAL, "block ILU0 needs block[3]");
@@ -925,7 +936,7 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
          *y = b + 5 * n, *z = b + 6 * n;
   double *part = ctx->d_red;
   PcgScalars *sc = ctx->d_sc;
-  const bool ilu = pc == STS_PC_BLOCK_ILU0;
+  const bool ilu = pc == STS_PC_BLOCK_ILU0, fpc = pc == STS_PC_FACTOR;
 
   launch_be_rhs(ctx, u_n, dt, b, invd, part + 2 * cap);
   LAUNCHCHK();
@@ -941,14 +952,20 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
     launch_ilu_apply_init(ctx, blk, fac, r, z);
     LAUNCHCHK();
   }
-  // both preconditioners keep z in its own array: pass A forms p = z + beta p
+  if (fpc) {  // z = G (G^T r)
+    launch_pc_gt(ctx, ctx->d_gfac, r, nullptr, ctx->d_pct, nullptr);
+    launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, nullptr, nullptr, nullptr);
+    LAUNCHCHK();
+  }
+  // every preconditioner keeps z in its own array: pass A forms p = z + beta p
   // from two streamed arrays
-  launch_init_p(ctx, r, invd, ilu ? z : nullptr, p0, part + 2 * cap, ilu ? nullptr : z);
+  const bool zgiven = ilu || fpc;
+  launch_init_p(ctx, r, invd, zgiven ? z : nullptr, p0, part + 2 * cap, zgiven ? nullptr : z);
   LAUNCHCHK();
   launch_finalize_init3(ctx, part + cap, part, part + 2 * cap, sc, rtol, maxit);
   LAUNCHCHK();
 
-  const int nb_parts = ilu ? ilu_parts(ctx, blk) : pass_b_parts(ctx);
+  const int nb_parts = ilu ? ilu_parts(ctx, blk) : (fpc ? pc_parts(ctx) : pass_b_parts(ctx));
   PcgScalars *h = (PcgScalars *)ctx->h_pin;
   double *pold = p0, *pnew = p1;
   HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
@@ -967,6 +984,14 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
       launch_finalize_alpha(ctx, part, np3, sc);
       launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
       launch_finalize_beta(ctx, part, nb_parts, sc);
+    } else if (fpc) {
+      // pass B updates x and r; z = G (G^T r) and the dots r.z, r.r follow
+      launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
+      launch_finalize_alpha(ctx, part, np3, sc);
+      launch_pass_b_xr(ctx, x, pnew, r, y, sc);
+      launch_pc_gt(ctx, ctx->d_gfac, r, nullptr, ctx->d_pct, sc);
+      launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, r, part, sc);
+      launch_finalize_beta(ctx, part, nb_parts, sc);
     } else {
       launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, nb_parts, it);
       launch_pass_b_jacobi_fused(ctx, x, pnew, r, y, invd, z, part_b, sc, part, np3);
@@ -974,7 +999,7 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
     std::swap(pold, pnew);
   });
   if (st) return st;
-  if (!ilu && maxit > 0 && !h->done) {
+  if (!ilu && !fpc && maxit > 0 && !h->done) {
     // every one of the maxit iterations ran; evaluate the last one's end
     launch_finalize_check(ctx, part_b, nb_parts, maxit, sc);
     LAUNCHCHK();
@@ -988,6 +1013,118 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   ctx->err = "PCG reached maxit";
   return STS_NOT_CONVERGED;
 }
+
+}  // extern "C"
+
+// ---- the factored preconditioner M^-1 = G G^T ------------------------------
+// (the sts_* entry points keep the C linkage of their declarations in sts.h)
+
+static sts_status pc_factor_storage(sts_ctx *ctx) {
+  if (!ctx->d_gfac) return dalloc(ctx, (void **)&ctx->d_gfac, (size_t)4 * ctx->ncell * 4);
+  return STS_OK;
+}
+
+sts_status sts_set_pc_factor(sts_ctx *ctx, const float *g) {
+  if (!ctx) return STS_EINVAL;
+  if (!g) FAIL(STS_EINVAL, "sts_set_pc_factor: null factor");
+  sts_status st = pc_factor_storage(ctx);
+  if (st) return st;
+  HIPCHK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+  launch_pc_check(ctx, g, ctx->d_flag);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(ctx->d_gfac, g, (size_t)4 * ctx->ncell * 4, hipMemcpyDeviceToDevice,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->h_pin, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (*(int *)ctx->h_pin) {
+    ctx->gfac_set = false;
+    FAIL(STS_EINVAL, "sts_set_pc_factor: diagonal entries must be finite and > 0, the others "
+                     "finite");
+  }
+  ctx->gfac_set = true;
+  return STS_OK;
+}
+
+// Network-built factor (cnn_pc_factor): o4 [cells][4] outputs (null: Jacobi).
+// Returns STS_BREAKDOWN (factor left unset) if an entry is not finite.
+sts_status sts::build_pc_factor(sts_ctx *ctx, double dt, const float *o4) {
+  sts_status st = pc_factor_storage(ctx);
+  if (st) return st;
+  HIPCHK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+  launch_pc_build(ctx, dt, o4, ctx->d_gfac, ctx->d_flag);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(ctx->h_pin, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->gfac_set = *(int *)ctx->h_pin == 0;
+  if (!ctx->gfac_set) FAIL(STS_BREAKDOWN, "factor with a non-finite entry");
+  return STS_OK;
+}
+
+sts_status sts_apply_pc_factor(sts_ctx *ctx, const double *r, double *z) {
+  if (!ctx) return STS_EINVAL;
+  if (!ctx->gfac_set) FAIL(STS_EINVAL, "sts_apply_pc_factor: no factor set");
+  if (!r || !z || r == z) FAIL(STS_EINVAL, "sts_apply_pc_factor: null or aliased arrays");
+  sts_status st;
+  if (!ctx->d_pct && (st = dalloc(ctx, (void **)&ctx->d_pct, (size_t)ctx->ncell * 8))) return st;
+  launch_pc_gt(ctx, ctx->d_gfac, r, nullptr, ctx->d_pct, nullptr);
+  launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, nullptr, nullptr, nullptr);
+  LAUNCHCHK();
+  return STS_OK;
+}
+
+// Vectors of the objective: w, y, r, q, s, p (scratch of pass A), 6 x ncell.
+static sts_status pc_objective_workspace(sts_ctx *ctx) {
+  sts_status st;
+  if ((st = ensure_red(ctx, std::max(pcg_parts(ctx), pc_parts(ctx))))) return st;
+  if (!ctx->d_pcobj && (st = dalloc(ctx, (void **)&ctx->d_pcobj, (size_t)6 * ctx->ncell * 8)))
+    return st;
+  if (!ctx->d_sc0) {
+    if ((st = dalloc(ctx, (void **)&ctx->d_sc0, sizeof(PcgScalars)))) return st;
+    HIPCHK(hipMemsetAsync(ctx->d_sc0, 0, sizeof(PcgScalars), ctx->stream));
+  }
+  return STS_OK;
+}
+
+// w = G z, y = A w, r = G^T y - z, q = G r, s = A q, then the gradient
+// kernel (dg and / or the network's output gradient dout) and r.r partials.
+sts_status sts::pc_objective_sweeps(sts_ctx *ctx, double dt, const double *z, double *dg,
+                                    void *dout) {
+  sts_status st = pc_objective_workspace(ctx);
+  if (st) return st;
+  const long long n = ctx->ncell;
+  double *w = ctx->d_pcobj, *y = w + n, *r = w + 2 * n, *q = w + 3 * n, *s = w + 4 * n,
+         *p = w + 5 * n;
+  double *part = ctx->d_red;
+  const float *g = ctx->d_gfac;
+  launch_pc_g(ctx, g, z, w, nullptr, nullptr, nullptr);
+  launch_pass_a(ctx, dt, w, nullptr, p, y, part, ctx->d_sc0, 1);
+  launch_pc_gt(ctx, g, y, z, r, nullptr);
+  launch_pc_g(ctx, g, r, q, nullptr, nullptr, nullptr);
+  launch_pass_a(ctx, dt, q, nullptr, p, s, part, ctx->d_sc0, 1);
+  launch_pc_grad(ctx, dt, g, y, r, s, z, dg, dout, part);
+  LAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status sts_pc_objective(sts_ctx *ctx, double dt, const double *z, double *loss, double *dg) {
+  if (!ctx || !loss) return STS_EINVAL;
+  if (ctx->op == OP_NONE) FAIL(STS_EINVAL, "no operator set");
+  if (ctx->prec != 0) FAIL(STS_EINVAL, "sts_pc_objective: FP64 operators only");
+  if (!ctx->gfac_set) FAIL(STS_EINVAL, "sts_pc_objective: no factor set");
+  if (!z) FAIL(STS_EINVAL, "sts_pc_objective: null z");
+  if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "dt must be finite, > 0");
+  sts_status st = sts::pc_objective_sweeps(ctx, dt, z, dg, nullptr);
+  if (st) return st;
+  launch_sum2(ctx, ctx->d_red, pc_parts(ctx), ctx->d_tmp);
+  LAUNCHCHK();
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, ctx->d_tmp, 16, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *loss = h[0] / (double)ctx->ncell;
+  return STS_OK;
+}
+
+extern "C" {
 
 sts_status sts_be_residual(sts_ctx *ctx, const double *u_n, const double *x, double dt,
                            double *relres) {

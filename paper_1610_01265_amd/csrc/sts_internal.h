@@ -103,6 +103,11 @@ struct sts_ctx {
   int red_cap = 0;
   sts::PcgScalars *d_sc = nullptr;
   sts::PcgScalars *h_sc = nullptr;  // pinned mirror
+  float *d_gfac = nullptr;    // factored preconditioner G, FP32 [4][ncell]
+  bool gfac_set = false;
+  double *d_pct = nullptr;    // its PCG work vector t = G^T r
+  double *d_pcobj = nullptr;  // sts_pc_objective: w, y, r, q, s, p (6 x ncell)
+  sts::PcgScalars *d_sc0 = nullptr;  // all-zero scalars: a stand-alone pass A (y = A p)
   double *d_ilu = nullptr;    // block ILU0 factors
   long long ilu_cap = 0;
   int *d_flag = nullptr;      // device flags (input checks, ILU breakdown)
@@ -244,5 +249,31 @@ void launch_pass_b_ilu(const sts_ctx *c, const int block[3], const double *fac, 
                        const double *p, double *r, const double *y, double *z, double *part,
                        const PcgScalars *sc);
 int ilu_parts(const sts_ctx *c, const int block[3]);
+
+// factored preconditioner M^-1 = G G^T (k_pc.hip); g: FP32 [4][ncell]
+int pc_parts(const sts_ctx *c);  // workgroups (partials) of the pc kernels
+// t = G^T x (- sub, may be null); sc (may be null): no-op once sc->done
+void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const double *sub,
+                  double *t, const PcgScalars *sc);
+// z = G t; r != null: partial sums r.z, r.r into part, part + red_cap
+void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z, const double *r,
+                 double *part, const PcgScalars *sc);
+// factor from network outputs o4 [cells][4] (null: point Jacobi) at dt
+void launch_pc_build(const sts_ctx *c, double dt, const float *o4, float *g, int *bad);
+void launch_pc_check(const sts_ctx *c, const float *g, int *bad);
+void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T, double tsh,
+                    double tsc, void *x);
+void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y,
+                    const double *r, const double *s, const double *z, double *dg, void *dout,
+                    double *part);
+void launch_pass_b_xr(const sts_ctx *c, double *x, const double *p, double *r, const double *y,
+                      const PcgScalars *sc);
+// host helpers of the factor network (sts_api.cpp): the factor built from
+// network outputs o4 [cells][4] at dt (STS_BREAKDOWN if an entry is not
+// finite), and the objective's sweeps at dt for probe z, writing dL/dG (dg)
+// and / or the network's output gradient (dout, bf16 [cells][16]) and the
+// r.r partials (pc_parts of them) into the context's reduction buffer
+sts_status build_pc_factor(sts_ctx *ctx, double dt, const float *o4);
+sts_status pc_objective_sweeps(sts_ctx *ctx, double dt, const double *z, double *dg, void *dout);
 
 }  // namespace sts

@@ -168,6 +168,112 @@ def summary(results):
     }
 
 
+# ---- the learned factor M^-1 = G G^T (STS_PC_FACTOR) ------------------------
+
+def probes(shape, count=8, seed=0):
+    """Seeded Rademacher probe vectors (+-1 per cell) on the device: the
+    random input of the factor's training objective."""
+    rng = np.random.default_rng(seed)
+    return [torch.from_numpy(rng.choice([-1.0, 1.0], size=tuple(shape))).cuda()
+            for _ in range(count)]
+
+
+def fit_factor_norm(net: B.CnnPC, fields):
+    """Temperature scalings of the factor network's input from the training
+    fields (host arrays)."""
+    m = np.mean([np.mean(T) for _, T in fields])
+    v = np.mean([np.mean(T * T) for _, T in fields]) - m * m
+    net.set_norm(m, 1.0 / np.sqrt(v))
+    return m, np.sqrt(v)
+
+
+def train_factor(prob: Problem, net: B.CnnPC, fields, ratio=200.0, epochs=2, lr=2e-3, seed=0,
+                 nprobe=8, log=None):
+    """Adam on the factor objective: for every training field (seed, T) the
+    operator is frozen at T, dt = ratio dt_E, and one step is taken with the
+    next probe vector; fields in seeded random order.  Returns the mean
+    objective per epoch."""
+    rng = np.random.default_rng(seed)
+    zs = probes(prob.shape, nprobe, seed)
+    dev = [(s, torch.from_numpy(T).cuda()) for s, T in fields]
+    hist, k = [], 0
+    for ep in range(epochs):
+        tot = 0.0
+        for q in rng.permutation(len(dev)):
+            _, T = dev[q]
+            dt = ratio * prob.set_temperature(T)
+            tot += net.train_step(T, dt, zs[k % nprobe], lr)
+            k += 1
+        hist.append(tot / len(dev))
+        if log:
+            log(f"factor epoch {ep}: mean objective {hist[-1]:.4g}")
+    return hist
+
+
+def solve_factor(ctx, u_n, x, dt, rtol=1e-8, maxit=20000):
+    """PCG with the context's factor; the fallback is Jacobi-PCG, from the
+    last iterate if the factor's solve did not reach rtol within maxit, from
+    the initial guess after a breakdown.  Returns (iterations, used_factor)."""
+    x0 = x.clone()
+    try:
+        it, _, st = ctx.be_pcg_solve(u_n, x, dt, B.PC_FACTOR, rtol=rtol, maxit=maxit,
+                                     allow_not_converged=True)
+    except B.StsError as e:
+        if e.code != B.STS_BREAKDOWN:
+            raise
+        x.copy_(x0)
+        it2, _, _ = ctx.be_pcg_solve(u_n, x, dt, B.PC_JACOBI, rtol=rtol, maxit=maxit)
+        return it2, False
+    if st == B.STS_OK:
+        return it, True
+    it2, _, _ = ctx.be_pcg_solve(u_n, x, dt, B.PC_JACOBI, rtol=rtol, maxit=maxit)
+    return it + it2, False
+
+
+def evaluate_factor(prob: Problem, net_pc: B.CnnPC, fields, ratio=200.0, rtol=1e-8,
+                    net_guess: B.Cnn | None = None):
+    """Per test field: Jacobi-PCG and factor-PCG from the previous-step guess
+    and (with a guess network) from the network's guess: iterations and
+    times (the factor's and the guess's set-up included)."""
+    out = []
+    ctx = prob.ctx
+    for seed, T_host in fields:
+        T = torch.from_numpy(T_host).cuda()
+        dt = ratio * prob.set_temperature(T)
+        res = GuessResult(seed)
+        runs = [("jacobi_previous", B.PC_JACOBI, False), ("factor_previous", B.PC_FACTOR, False)]
+        if net_guess is not None:
+            runs += [("jacobi_network", B.PC_JACOBI, True), ("factor_network", B.PC_FACTOR, True)]
+        for name, pc, use_guess in runs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if use_guess:
+                x, _, _ = net_guess.guess(T, dt)
+            else:
+                x = T.clone()
+            if pc == B.PC_FACTOR:
+                used = net_pc.factor(T, dt)
+                it, ok = solve_factor(ctx, T, x, dt, rtol)
+                res.used_net = res.used_net and used and ok
+            else:
+                it, _, _ = ctx.be_pcg_solve(T, x, dt, pc, rtol=rtol)
+            torch.cuda.synchronize()
+            res.seconds[name] = time.perf_counter() - t0
+            res.iters[name] = it
+        out.append(res)
+    return out
+
+
+def factor_summary(results):
+    names = list(results[0].iters)
+    return {
+        "mean_iters": {n: float(np.mean([r.iters[n] for r in results])) for n in names},
+        "mean_seconds": {n: float(np.mean([r.seconds[n] for r in results])) for n in names},
+        "factor_kept": int(sum(r.used_net for r in results)),
+        "cases": len(results),
+    }
+
+
 def run(shape=(128, 128, 256), train_seeds=range(200), test_seeds=range(200, 250), ratio=200.0,
         epochs=4, lr=1e-3, init_seed=0, train_rtol=1e-10, rtol=1e-8, workers=8, log=print):
     """The whole learned-guess protocol; returns (summary, per-seed results, timings).

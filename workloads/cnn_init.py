@@ -1,7 +1,8 @@
 """Seeded initial weights of the learned-guess CNN and the flat weight-vector
 layout of the C ABI (cnn_set_weights).  Random draws and array layout only.
 
-Network: `layers` 3x3x3 convolutions, 2 -> channels -> ... -> channels -> 1.
+Network: `layers` 3x3x3 convolutions, 2 -> channels -> ... -> channels -> out_ch
+(1 for the initial-guess network, 4 for the factor network).
 Flat vector, per layer l: W[c_out][c_in][3][3][3] then bias[c_out].
 """
 from __future__ import annotations
@@ -13,10 +14,10 @@ def layer_dims(layers: int = 4, channels: int = 16, in_ch: int = 2, out_ch: int 
     return [in_ch] + [channels] * (layers - 1) + [out_ch]
 
 
-def he_normal(layers: int = 4, channels: int = 16, seed: int = 0):
+def he_normal(layers: int = 4, channels: int = 16, seed: int = 0, out_ch: int = 1):
     """[(W, b)] with W ~ N(0, 2 / fan_in), fan_in = 27 c_in, and zero biases."""
     rng = np.random.default_rng(seed)
-    d = layer_dims(layers, channels)
+    d = layer_dims(layers, channels, out_ch=out_ch)
     out = []
     for l in range(layers):
         W = rng.standard_normal((d[l + 1], d[l], 3, 3, 3)) * np.sqrt(2.0 / (27 * d[l]))
@@ -29,8 +30,8 @@ def flatten(params) -> np.ndarray:
                           ).astype(np.float32)
 
 
-def unflatten(vec, layers: int = 4, channels: int = 16):
-    d = layer_dims(layers, channels)
+def unflatten(vec, layers: int = 4, channels: int = 16, out_ch: int = 1):
+    d = layer_dims(layers, channels, out_ch=out_ch)
     vec = np.asarray(vec, np.float64)
     out, q = [], 0
     for l in range(layers):

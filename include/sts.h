@@ -63,6 +63,25 @@ const char *sts_last_error(const sts_ctx *ctx);
 /* number of cells n0*n1*n2 */
 long long sts_num_cells(const sts_ctx *ctx);
 
+/* Diagnostics (not in the paper).
+ * sts_set_profile - per-kernel timing on (on != 0) or off; the environment
+ * variable STS_PROFILE (set and not "0") switches it on at sts_create.  While
+ * on, every kernel launch of the library is bracketed by a pair of HIP events
+ * on the context's stream.
+ * sts_profile_summary - writes a text table into buf (HOST, cap bytes): one
+ * line per launcher, "calls total_ms avg_us min_us max_us name", by total
+ * time; reset != 0 clears the records.  STS_EINVAL if buf is too small.
+ * Synchronises the stream.
+ * sts_set_debug - flags; STS_DEBUG_WG_REVERSE makes the stencil, PCG and
+ * factor kernels take their work in reversed workgroup order (each
+ * workgroup still computes the same tiles and partial sums), a self-check
+ * that results do not depend on the order in which workgroups run: results
+ * are bit for bit those of the normal order.  */
+enum { STS_DEBUG_WG_REVERSE = 1 };
+sts_status sts_set_profile(sts_ctx *ctx, int on);
+sts_status sts_profile_summary(sts_ctx *ctx, char *buf, long long cap, int reset);
+sts_status sts_set_debug(sts_ctx *ctx, int flags);
+
 /* sts_set_spitzer - lagged-diffusivity conduction operator (Sec. 1; Eq.
  * mhd:e1, blue box): D = kappa0 T^{5/2} b b^T with T (> 0) and the unit
  * vector b = (b0, b1, b2) in the local (r, theta, phi) basis, all device FP64

@@ -16,6 +16,7 @@ STS_EINVAL, STS_EHIP, STS_ENOMEM, STS_BREAKDOWN = -1, -2, -3, -4
 SPHERICAL, CARTESIAN = 0, 1
 BC_ZEROFLUX, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 PC_JACOBI, PC_BLOCK_ILU0, PC_FACTOR = 0, 1, 2
+DEBUG_WG_REVERSE = 1
 SHELL_BC = (BC_DIRICHLET, BC_ZEROFLUX, BC_ZEROFLUX, BC_ZEROFLUX, BC_PERIODIC, BC_PERIODIC)
 
 _STATUS = {0: "STS_OK", 1: "STS_NOT_CONVERGED", -1: "STS_EINVAL", -2: "STS_EHIP",
@@ -89,6 +90,9 @@ def load():
         "cnn_pc_factor": (I, [P, P, D, PI]),
         "cnn_pc_train_step": (I, [P, P, D, P, ctypes.c_float, PD]),
         "cnn_pc_grad": (I, [P, P, D, P, P, PD]),
+        "sts_set_profile": (I, [P, I]),
+        "sts_profile_summary": (I, [P, ctypes.c_char_p, ctypes.c_longlong, I]),
+        "sts_set_debug": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -110,7 +114,7 @@ def exported_symbols():
             "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_set_adam", "cnn_adam_step",
             "cnn_guess", "sts_set_pc_factor", "sts_apply_pc_factor", "sts_pc_objective",
             "cnn_create_pc", "cnn_pc_set_norm", "cnn_pc_factor", "cnn_pc_train_step",
-            "cnn_pc_grad"]
+            "cnn_pc_grad", "sts_set_profile", "sts_profile_summary", "sts_set_debug"]
 
 
 def _ptr(t: torch.Tensor | None, ncell: int, name: str, ncomp: int | None = 1,
@@ -326,6 +330,23 @@ class Context:
                                     ctypes.byref(rel))
         self._check(st, (STS_OK, STS_NOT_CONVERGED) if allow_not_converged else (STS_OK,))
         return it.value, rel.value, st
+
+    def set_profile(self, on=True):
+        self._check(self._lib.sts_set_profile(self._h, 1 if on else 0))
+
+    def profile_summary(self, reset=True, cap=1 << 16):
+        """Per-launcher timing table: {name: (calls, total_ms, avg_us, min_us, max_us)}."""
+        self._sync_stream()
+        buf = ctypes.create_string_buffer(cap)
+        self._check(self._lib.sts_profile_summary(self._h, buf, cap, 1 if reset else 0))
+        out = {}
+        for line in buf.value.decode().splitlines()[1:]:
+            f = line.split()
+            out[f[5]] = (int(f[0]), float(f[1]), float(f[2]), float(f[3]), float(f[4]))
+        return out
+
+    def set_debug(self, flags):
+        self._check(self._lib.sts_set_debug(self._h, int(flags)))
 
     def set_pc_factor(self, g):
         """The STS_PC_FACTOR factor from a device FP32 tensor [4, n0, n1, n2]."""
@@ -639,6 +660,18 @@ def cnn_pc_train_step(net: CnnPC, T, dt, z, lr, want_loss=True):
 
 def cnn_pc_grad(net: CnnPC, T, dt, z, out=None):
     return net.grad(T, dt, z, out)
+
+
+def sts_set_profile(ctx: Context, on=True):
+    ctx.set_profile(on)
+
+
+def sts_profile_summary(ctx: Context, reset=True):
+    return ctx.profile_summary(reset)
+
+
+def sts_set_debug(ctx: Context, flags):
+    ctx.set_debug(flags)
 
 
 def sts_set_pc_factor(ctx: Context, g):

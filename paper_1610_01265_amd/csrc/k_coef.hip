@@ -197,11 +197,13 @@ void spitzer_coef(const sts_ctx *c, const TI *T, double kappa0, const TI *b0, co
 
 void launch_spitzer_coef(const sts_ctx *c, const double *T, double kappa0, const double *b0,
                          const double *b1, const double *b2) {
+  STS_PROF(c, "launch_spitzer_coef");
   spitzer_coef<double>(c, T, kappa0, b0, b1, b2);
 }
 
 void launch_spitzer_coef_f32(const sts_ctx *c, const float *T, double kappa0, const float *b0,
                              const float *b1, const float *b2) {
+  STS_PROF(c, "launch_spitzer_coef_f32");
   spitzer_coef<float>(c, T, kappa0, b0, b1, b2);
   const long long n = 6 * c->ncell;
   hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->d_w,
@@ -209,6 +211,7 @@ void launch_spitzer_coef_f32(const sts_ctx *c, const float *T, double kappa0, co
 }
 
 void launch_dirichlet_weights(const sts_ctx *c) {
+  STS_PROF(c, "launch_dirichlet_weights");
   // isotropic operator: weights from geometry and nu only
   const int nb = c->n1 * c->n2;
   hipLaunchKernelGGL(k_dirichlet_w<double>, dim3((nb + 255) / 256), dim3(256), 0, c->stream,
@@ -217,6 +220,7 @@ void launch_dirichlet_weights(const sts_ctx *c) {
 }
 
 void launch_sdiag(const sts_ctx *c) {
+  STS_PROF(c, "launch_sdiag");
   if (c->op == OP_SPITZER)
     hipLaunchKernelGGL(k_sdiag<OP_SPITZER>, grid3(c), dim3(TX, TY), 0, c->stream, c->grid(),
                        c->coef(), c->d_sdiag);
@@ -226,12 +230,14 @@ void launch_sdiag(const sts_ctx *c) {
 }
 
 void launch_fill(const sts_ctx *c, double *p, long long n, double v) {
+  STS_PROF(c, "launch_fill");
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p, n, v);
 }
 
 void launch_check_spitzer(const sts_ctx *c, const double *T, const double *b0, const double *b1,
                           const double *b2, int *flag) {
+  STS_PROF(c, "launch_check_spitzer");
   const long long n = c->ncell;
   hipLaunchKernelGGL(k_check_spitzer<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      c->stream, n, T, b0, b1, b2, flag);
@@ -239,6 +245,7 @@ void launch_check_spitzer(const sts_ctx *c, const double *T, const double *b0, c
 
 void launch_check_spitzer_f32(const sts_ctx *c, const float *T, const float *b0, const float *b1,
                               const float *b2, int *flag) {
+  STS_PROF(c, "launch_check_spitzer_f32");
   const long long n = c->ncell;
   hipLaunchKernelGGL(k_check_spitzer<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      c->stream, n, T, b0, b1, b2, flag);
@@ -250,6 +257,7 @@ int gershgorin_parts(const sts_ctx *c) {
 }
 
 void launch_gershgorin(const sts_ctx *c, double *partials, int) {
+  STS_PROF(c, "launch_gershgorin");
   if (c->op == OP_SPITZER)
     hipLaunchKernelGGL(k_gershgorin<OP_SPITZER>, grid3(c), dim3(TX, TY), 0, c->stream,
                        c->grid(), c->coef(), partials);

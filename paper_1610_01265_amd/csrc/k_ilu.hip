@@ -510,6 +510,7 @@ int ilu_parts(const sts_ctx *c, const int block[3]) {
 }
 
 void launch_ilu_factor(const sts_ctx *c, double dt, const int block[3], double *fac, int *bad) {
+  STS_PROF(c, "launch_ilu_factor");
   const int nb = ilu_nblocks(c, block);
   if (c->op == OP_SPITZER)
     hipLaunchKernelGGL(k_ilu_factor<OP_SPITZER>, dim3(nb), dim3(FTH), 0, c->stream, c->grid(),
@@ -521,6 +522,7 @@ void launch_ilu_factor(const sts_ctx *c, double dt, const int block[3], double *
 
 void launch_ilu_apply_init(const sts_ctx *c, const int block[3], const double *fac,
                            const double *r, double *z) {
+  STS_PROF(c, "launch_ilu_apply_init");
   const int nb = ilu_nblocks(c, block);
   if (is8(block)) {
     hipLaunchKernelGGL(k_ilu_apply8<false>, dim3(ilu8_grid(nb)), dim3(ATH), 0, c->stream,
@@ -539,6 +541,7 @@ void launch_ilu_apply_init(const sts_ctx *c, const int block[3], const double *f
 void launch_pass_b_ilu(const sts_ctx *c, const int block[3], const double *fac, double *x,
                        const double *p, double *r, const double *y, double *z, double *part,
                        const PcgScalars *sc) {
+  STS_PROF(c, "launch_pass_b_ilu");
   const int nb = ilu_nblocks(c, block);
   if (is8(block)) {
     hipLaunchKernelGGL(k_ilu_apply8<true>, dim3(ilu8_grid(nb)), dim3(ATH), 0, c->stream,

@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(NNT) k_march_nl(Grid g, CoefS<double> C, NlArg
   const int tid = tj * NK + tk;
   // XCD-aware order (workgroup w runs on XCD w % 8; each XCD gets a
   // contiguous range of the logical (chunk, row-tile, column-tile) order)
-  const int nwg = gridDim.x, w = blockIdx.x;
+  const int nwg = gridDim.x, w = wg_index(g.wg_rev);
   const int q8 = nwg >> 3, r8 = nwg & 7, x8 = w & 7, s8 = w >> 3;
   const int L = x8 < r8 ? x8 * (q8 + 1) + s8 : r8 * (q8 + 1) + (x8 - r8) * q8 + s8;
   const int ntk = (g.n2 + NK - 1) / NK, ntj = (g.n1 + NJ - 1) / NJ;
@@ -378,6 +378,7 @@ void launch_stage_nl(const sts_ctx *c, int mode, const double *ukm1, const doubl
                      const double *u0, double *F0, double *out, double mu, double nu,
                      double mut_dt, double gt_dt, double kappa0, const double *b0,
                      const double *b1, const double *b2) {
+  STS_PROF(c, "launch_stage_nl");
   NlArgs a{ukm1, ukm2, u0, b0, b1, b2, F0, out, kappa0, mu, nu, mut_dt, gt_dt};
   const Coef k = c->coef();
   CoefS<double> C{};

@@ -33,6 +33,7 @@ struct PcDims {
   long long n12, n;
   int ntx, nty;
   long long items;
+  int rev;  // debug: reversed workgroup order
 };
 
 PcDims dims_of(const sts_ctx *c) {
@@ -45,13 +46,14 @@ PcDims dims_of(const sts_ctx *c) {
   d.ntx = (c->n2 + TX - 1) / TX;
   d.nty = (c->n1 + TY - 1) / TY;
   d.items = (long long)d.ntx * d.nty * c->n0;
+  d.rev = (c->debug & STS_DEBUG_WG_REVERSE) ? 1 : 0;
   return d;
 }
 
 // Visit every cell once: workgroups stride over (tile, plane) items.
 template <class F>
 __device__ __forceinline__ void for_cells(const PcDims &d, F &&f) {
-  for (long long it = blockIdx.x; it < d.items; it += gridDim.x) {
+  for (long long it = wg_index(d.rev); it < d.items; it += gridDim.x) {
     const int bx = (int)(it % d.ntx);
     const long long r = it / d.ntx;
     const int by = (int)(r % d.nty);
@@ -98,8 +100,8 @@ __global__ void __launch_bounds__(NT)
     }
   });
   if (DOTS)
-    wg_sum2<NT>(rz, rr, threadIdx.y * TX + threadIdx.x, part + blockIdx.x,
-                part + cap + blockIdx.x);
+    wg_sum2<NT>(rz, rr, threadIdx.y * TX + threadIdx.x, part + wg_index(d.rev),
+                part + cap + wg_index(d.rev));
 }
 
 // 1 / sqrt(A_cc), A_cc = V - dt S_cc
@@ -210,18 +212,19 @@ __global__ void __launch_bounds__(NT)
       dst[1] = hi;
     }
   });
-  wg_sum2<NT>(rr, 0.0, threadIdx.y * TX + threadIdx.x, part + blockIdx.x, nullptr);
+  wg_sum2<NT>(rr, 0.0, threadIdx.y * TX + threadIdx.x, part + wg_index(d.rev), nullptr);
 }
 
 // x += alpha p, r -= alpha y (alpha from the finalizer); no preconditioner
 // and no dots: those follow in k_pc_gt / k_pc_g<true>
 __global__ void __launch_bounds__(NT)
     k_pass_b_xr(long long n, double *__restrict__ x, const double *__restrict__ p,
-                double *__restrict__ r, const double *__restrict__ y, const PcgScalars *sc) {
+                double *__restrict__ r, const double *__restrict__ y, const PcgScalars *sc,
+                int rev) {
   if (sc->done) return;
   const double alpha = sc->alpha;
   const long long stride = (long long)gridDim.x * NT;
-  for (long long c = (long long)blockIdx.x * NT + threadIdx.y * TX + threadIdx.x; c < n;
+  for (long long c = (long long)wg_index(rev) * NT + threadIdx.y * TX + threadIdx.x; c < n;
        c += stride) {
     x[c] = x[c] + alpha * p[c];
     r[c] = r[c] - alpha * y[c];
@@ -236,6 +239,7 @@ int pc_parts(const sts_ctx *c) { return grid_items(dims_of(c)); }
 
 void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const double *sub,
                   double *t, const PcgScalars *sc) {
+  STS_PROF(c, "launch_pc_gt");
   const PcDims d = dims_of(c);
   hipLaunchKernelGGL(k_pc_gt, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, x, sub, t,
                      sc);
@@ -243,6 +247,7 @@ void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const doubl
 
 void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z, const double *r,
                  double *part, const PcgScalars *sc) {
+  STS_PROF(c, "launch_pc_g");
   const PcDims d = dims_of(c);
   if (r)
     hipLaunchKernelGGL(k_pc_g<true>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, t,
@@ -253,18 +258,21 @@ void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z, c
 }
 
 void launch_pc_build(const sts_ctx *c, double dt, const float *o4, float *g, int *bad) {
+  STS_PROF(c, "launch_pc_build");
   const PcDims d = dims_of(c);
   hipLaunchKernelGGL(k_pc_build, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
                      (const double *)c->d_sdiag, dt, o4, g, bad);
 }
 
 void launch_pc_check(const sts_ctx *c, const float *g, int *bad) {
+  STS_PROF(c, "launch_pc_check");
   const PcDims d = dims_of(c);
   hipLaunchKernelGGL(k_pc_check, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, bad);
 }
 
 void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T, double tsh,
                     double tsc, void *x) {
+  STS_PROF(c, "launch_pc_pack");
   const PcDims d = dims_of(c);
   hipLaunchKernelGGL(k_pc_pack, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
                      (const double *)c->d_sdiag, dt, lscale, T, tsh, tsc, (__bf16 *)x);
@@ -273,6 +281,7 @@ void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T,
 void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y,
                     const double *r, const double *s, const double *z, double *dg, void *dout,
                     double *part) {
+  STS_PROF(c, "launch_pc_grad");
   const PcDims d = dims_of(c);
   hipLaunchKernelGGL(k_pc_grad, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
                      (const double *)c->d_sdiag, dt, g, y, r, s, z, dg, (__bf16 *)dout, part);
@@ -280,10 +289,11 @@ void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y
 
 void launch_pass_b_xr(const sts_ctx *c, double *x, const double *p, double *r, const double *y,
                       const PcgScalars *sc) {
+  STS_PROF(c, "launch_pass_b_xr");
   const long long n = c->ncell;
   const long long nb = (n + NT - 1) / NT;
   hipLaunchKernelGGL(k_pass_b_xr, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(TX, TY), 0,
-                     c->stream, n, x, p, r, y, sc);
+                     c->stream, n, x, p, r, y, sc, (c->debug & STS_DEBUG_WG_REVERSE) ? 1 : 0);
 }
 
 }  // namespace sts

@@ -50,16 +50,17 @@ __global__ void __launch_bounds__(NT)
 __global__ void __launch_bounds__(NT)
     k_init_p(long long n, const double *__restrict__ r, const double *__restrict__ invd,
              const double *__restrict__ zilu, double *__restrict__ p, double *part,
-             double *__restrict__ zout) {
+             double *__restrict__ zout, int rev) {
   double rz = 0.0;
   const long long stride = (long long)gridDim.x * NT;
-  for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
+  const int w = wg_index(rev);
+  for (long long c = (long long)w * NT + threadIdx.x; c < n; c += stride) {
     const double z = zilu ? zilu[c] : r[c] * invd[c];
     if (zout) zout[c] = z;
     p[c] = z;
     rz += r[c] * z;
   }
-  wg_sum2<NT>(rz, 0.0, threadIdx.x, part + blockIdx.x, nullptr);
+  wg_sum2<NT>(rz, 0.0, threadIdx.x, part + w, nullptr);
 }
 
 __global__ void k_fin_init(const double *pb, int nb, const double *prr, int nrr,
@@ -120,7 +121,7 @@ __global__ void __launch_bounds__(NT)
     k_pass_b_jac(long long n, double *__restrict__ x, const double *__restrict__ p,
                  double *__restrict__ r, const double *__restrict__ y,
                  const double *__restrict__ invd, double *__restrict__ zout, double *part,
-                 long long cap, PcgScalars *sc, const double *pa, int npa) {
+                 long long cap, PcgScalars *sc, const double *pa, int npa, int rev) {
   if (sc->done) return;
   double alpha;
   if (FUSE) {
@@ -130,7 +131,8 @@ __global__ void __launch_bounds__(NT)
   }
   double rz = 0.0, rr = 0.0;
   const long long stride = (long long)gridDim.x * NT;
-  for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += stride) {
+  const int w = wg_index(rev);
+  for (long long c = (long long)w * NT + threadIdx.x; c < n; c += stride) {
     x[c] = x[c] + alpha * p[c];
     const double rn = r[c] - alpha * y[c];
     r[c] = rn;
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__(NT)
     rz += rn * zn;
     rr += rn * rn;
   }
-  wg_sum2<NT>(rz, rr, threadIdx.x, part + blockIdx.x, part + cap + blockIdx.x);
+  wg_sum2<NT>(rz, rr, threadIdx.x, part + w, part + cap + w);
 }
 
 __global__ void k_fin_beta(const double *part, int n, long long cap, PcgScalars *sc) {
@@ -248,6 +250,8 @@ __global__ void k_sum2(const double *part, int n, long long cap, double *out) {
   }
 }
 
+int rev_of(const sts_ctx *c) { return (c->debug & STS_DEBUG_WG_REVERSE) ? 1 : 0; }
+
 dim3 grid3(const sts_ctx *c) {
   return dim3((c->n2 + TX - 1) / TX, (c->n1 + TY - 1) / TY, c->n0);
 }
@@ -264,6 +268,7 @@ int pcg_parts(const sts_ctx *c) {
 
 void launch_be_rhs(const sts_ctx *c, const double *u_n, double dt, double *b, double *invd,
                    double *part) {
+  STS_PROF(c, "launch_be_rhs");
   if (c->op == OP_SPITZER)
     hipLaunchKernelGGL(k_be_rhs<OP_SPITZER>, grid3(c), dim3(TX, TY), 0, c->stream, c->grid(),
                        c->coef(), u_n, dt, c->d_sdiag, b, invd);
@@ -274,20 +279,23 @@ void launch_be_rhs(const sts_ctx *c, const double *u_n, double dt, double *b, do
 
 void launch_init_p(const sts_ctx *c, const double *r, const double *invd, const double *zilu,
                    double *p, double *part, double *zout) {
+  STS_PROF(c, "launch_init_p");
   const long long n = c->ncell;
   hipLaunchKernelGGL(k_init_p, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, n,
-                     r, invd, zilu, p, part, zout);
+                     r, invd, zilu, p, part, zout, rev_of(c));
 }
 
 void launch_finalize_init_n(const sts_ctx *c, const double *pb, int nb, const double *prr,
                             int nrr, const double *prz, int nrz, PcgScalars *sc, double rtol,
                             int maxit) {
+  STS_PROF(c, "launch_finalize_init_n");
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(256), 0, c->stream, pb, nb, prr, nrr, prz, nrz, sc,
                      rtol, maxit);
 }
 
 void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr,
                            const double *prz, PcgScalars *sc, double rtol, int maxit) {
+  STS_PROF(c, "launch_finalize_init3");
   const int n3 = stencil_parts(c);
   const int n1 = pass_b_parts(c);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(256), 0, c->stream, pb, n3, prr, n3, prz, n1, sc,
@@ -296,40 +304,47 @@ void launch_finalize_init3(const sts_ctx *c, const double *pb, const double *prr
 
 void launch_init_p_n(const sts_ctx *c, long long n, const double *r, const double *invd,
                      double *p, double *part, int nparts) {
+  STS_PROF(c, "launch_init_p_n");
   hipLaunchKernelGGL(k_init_p, dim3(nparts), dim3(NT), 0, c->stream, n, r, invd,
-                     (const double *)nullptr, p, part, (double *)nullptr);
+                     (const double *)nullptr, p, part, (double *)nullptr, rev_of(c));
 }
 
 void launch_pass_b_jacobi_n(const sts_ctx *c, long long n, double *x, const double *p, double *r,
                             const double *y, const double *invd, double *part, int nparts,
                             const PcgScalars *sc, const double *pa, int npa) {
+  STS_PROF(c, "launch_pass_b_jacobi_n");
   PcgScalars *s = const_cast<PcgScalars *>(sc);
   if (pa)
     hipLaunchKernelGGL(k_pass_b_jac<true>, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y,
-                       invd, (double *)nullptr, part, cap_of(c), s, pa, npa);
+                       invd, (double *)nullptr, part, cap_of(c), s, pa, npa, rev_of(c));
   else
     hipLaunchKernelGGL(k_pass_b_jac<false>, dim3(nparts), dim3(NT), 0, c->stream, n, x, p, r, y,
-                       invd, (double *)nullptr, part, cap_of(c), s, (const double *)nullptr, 0);
+                       invd, (double *)nullptr, part, cap_of(c), s, (const double *)nullptr, 0,
+                       rev_of(c));
 }
 
 void launch_finalize_alpha(const sts_ctx *c, const double *part, int, PcgScalars *sc) {
+  STS_PROF(c, "launch_finalize_alpha");
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, c->stream, part, stencil_parts(c), sc);
 }
 
 void launch_pass_b_jacobi_fused(const sts_ctx *c, double *x, const double *p, double *r,
                                 const double *y, const double *invd, double *z, double *part,
                                 PcgScalars *sc, const double *pa, int npa) {
+  STS_PROF(c, "launch_pass_b_jacobi_fused");
   hipLaunchKernelGGL(k_pass_b_jac<true>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell,
-                     x, p, r, y, invd, z, part, cap_of(c), sc, pa, npa);
+                     x, p, r, y, invd, z, part, cap_of(c), sc, pa, npa, rev_of(c));
 }
 
 void launch_finalize_check(const sts_ctx *c, const double *part, int nparts, int iters,
                            PcgScalars *sc) {
+  STS_PROF(c, "launch_finalize_check");
   hipLaunchKernelGGL(k_fin_check, dim3(1), dim3(256), 0, c->stream, part, nparts, cap_of(c), iters,
                      sc);
 }
 
 void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgScalars *sc) {
+  STS_PROF(c, "launch_finalize_beta");
   hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, c->stream, part, nparts, cap_of(c), sc);
 }
 
@@ -339,6 +354,7 @@ int pass_b_parts(const sts_ctx *c) {
 }
 
 void launch_sum2(const sts_ctx *c, const double *part, int nparts, double *out2) {
+  STS_PROF(c, "launch_sum2");
   hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, c->stream, part, nparts, cap_of(c), out2);
 }
 
@@ -349,6 +365,7 @@ namespace sts {
 
 void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, float *r,
                     float *invd, float *e, float *z, double *part) {
+  STS_PROF(c, "f32_inner_init");
   hipLaunchKernelGGL(k_f32_init, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, r64,
                      invd64, r, invd, e, z, part, (long long)c->red_cap);
 }
@@ -356,6 +373,7 @@ void f32_inner_init(const sts_ctx *c, const double *r64, const double *invd64, f
 void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const float *y,
                 const float *invd, float *z, double *part, const PcgScalars *sc,
                 const double *pa, int npa) {
+  STS_PROF(c, "f32_pass_b");
   PcgScalars *s = const_cast<PcgScalars *>(sc);
   if (pa)
     hipLaunchKernelGGL(k_f32_pass_b<true>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream,
@@ -367,10 +385,12 @@ void f32_pass_b(const sts_ctx *c, float *e, const float *p, float *r, const floa
 }
 
 void f32_add_to(const sts_ctx *c, double *x, const float *e) {
+  STS_PROF(c, "f32_add_to");
   hipLaunchKernelGGL(k_f32_add, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream, c->ncell, x, e);
 }
 
 void launch_fill_f32(const sts_ctx *c, float *p, long long n, float v) {
+  STS_PROF(c, "launch_fill_f32");
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p,
                      n, v);

@@ -338,6 +338,7 @@ static void curlT_launch(const sts_ctx *c, const RDims &d, const double *Phi, co
 }
 
 void launch_res_F(const sts_ctx *c, const double *E, double *Phi, double *FE) {
+  STS_PROF(c, "launch_res_F");
   const RDims d = rdims(c);
   curl_launch<0, RK_FLUX>(c, d, E, Phi);
   RArgs a{};
@@ -347,6 +348,7 @@ void launch_res_F(const sts_ctx *c, const double *E, double *Phi, double *FE) {
 }
 
 void launch_res_gershgorin(const sts_ctx *c, double *Phi, double *part) {
+  STS_PROF(c, "launch_res_gershgorin");
   const RDims d = rdims(c);
   curl_launch<0, RK_COUNT>(c, d, nullptr, Phi);
   RArgs a{};
@@ -360,6 +362,7 @@ void launch_res_gershgorin(const sts_ctx *c, double *Phi, double *part) {
 // edges := E^n's; partial b . b.  Wf receives the face weights.
 void launch_res_rhs(const sts_ctx *c, const double *En, double dt, double *x, double *b,
                     double *invd, double *Phi, double *Wf, double *part) {
+  STS_PROF(c, "launch_res_rhs");
   const RDims d = rdims(c);
   curl_launch<0, RK_WEIGHT>(c, d, nullptr, Wf);
   curl_launch<2, RK_FLUX>(c, d, En, Phi);
@@ -376,6 +379,7 @@ void launch_res_rhs(const sts_ctx *c, const double *En, double dt, double *x, do
 
 void launch_res_residual(const sts_ctx *c, const double *b, const double *x, double dt,
                          double *Phi, double *r, double *part) {
+  STS_PROF(c, "launch_res_residual");
   const RDims d = rdims(c);
   curl_launch<1, RK_FLUX>(c, d, x, Phi);
   RArgs a{};
@@ -391,6 +395,7 @@ void launch_res_residual(const sts_ctx *c, const double *b, const double *x, dou
 void launch_res_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
                        const double *pold, double *p, double *Phi, double *y, double *part,
                        const PcgScalars *sc, int first, const double *pb, int npb, int iters) {
+  STS_PROF(c, "launch_res_pass_a");
   const RDims d = rdims(c);
   const long long n = d.ne[0] + d.ne[1] + d.ne[2];
   hipLaunchKernelGGL(k_rpa, dim3(res_parts(c)), dim3(RT), 0, c->stream, n, r, invd, pold, p,

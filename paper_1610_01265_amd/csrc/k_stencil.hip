@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   const int tid = tj * TK + tk;
   // XCD-aware order: workgroup w runs on XCD w % 8; each XCD gets a
   // contiguous range of the logical (chunk, row-tile, column-tile) order.
-  const int nwg = gridDim.x, w = blockIdx.x;
+  const int nwg = gridDim.x, w = wg_index(g.wg_rev);
   const int q8 = nwg >> 3, r8 = nwg & 7, x8 = w & 7, s8 = w >> 3;
   const int L = x8 < r8 ? x8 * (q8 + 1) + s8 : r8 * (q8 + 1) + (x8 - r8) * q8 + s8;
   const int ntk = (g.n2 + TK - 1) / TK, ntj = (g.n1 + TJ - 1) / TJ;
@@ -466,6 +466,7 @@ int stencil_parts(const sts_ctx *c) {
 void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, const double *ukm2,
                   const double *u0, double *F0, double *out, double mu, double nu, double mut_dt,
                   double gt_dt) {
+  STS_PROF(c, mode == 0 ? "stage_F" : (mode == 1 ? "stage_rk_first" : "stage_rk"));
   Args a{};
   a.out = out;
   a.F0 = F0;
@@ -487,6 +488,7 @@ void launch_stage(const sts_ctx *c, int mode, int ncomp, const double *ukm1, con
 void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *pold,
                    double *pnew, double *y, double *part, const PcgScalars *sc, int first,
                    const double *pb, int npb, int iters) {
+  STS_PROF(c, "launch_pass_a");
   Args a{};
   a.out = pnew;
   a.y = y;
@@ -503,6 +505,7 @@ void launch_pass_a(const sts_ctx *c, double dt, const double *z, const double *p
 
 void launch_residual_init(const sts_ctx *c, const double *b, const double *x, double dt,
                           const double *, const double *, double *r, double *, double *part) {
+  STS_PROF(c, "launch_residual_init");
   Args a{};
   a.out = r;
   a.b = b;
@@ -514,6 +517,7 @@ void launch_residual_init(const sts_ctx *c, const double *b, const double *x, do
 
 void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,
                           double *part) {
+  STS_PROF(c, "launch_true_residual");
   Args a{};
   a.b = b;
   a.part = part;
@@ -542,6 +546,7 @@ void launch_f32(const sts_ctx *c, int ncomp, const Loader &ld, const Args &a) {
 }  // namespace
 
 void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1, double mut_dt) {
+  STS_PROF(c, "f32_F0");
   Args a{};
   a.F0 = F0;
   a.out = d1;
@@ -550,6 +555,7 @@ void f32_F0(const sts_ctx *c, int ncomp, const double *u0, float *F0, float *d1,
 }
 
 void f32_apply(const sts_ctx *c, int ncomp, const double *u, double *Fu) {
+  STS_PROF(c, "f32_apply");
   Args a{};
   a.out = Fu;
   launch_f32<M_F>(c, ncomp, LoadU<double>{u}, a);
@@ -558,6 +564,7 @@ void f32_apply(const sts_ctx *c, int ncomp, const double *u, double *Fu) {
 void f32_stage(const sts_ctx *c, int last, int ncomp, const float *dkm1, const float *dkm2,
                const float *F0, void *out, const double *u0, double mu, double nu, double mut_dt,
                double g_dt) {
+  STS_PROF(c, "f32_stage");
   Args a{};
   a.out = out;
   a.ukm2 = dkm2;
@@ -576,6 +583,7 @@ void f32_stage(const sts_ctx *c, int last, int ncomp, const float *dkm1, const f
 void f32_pass_a(const sts_ctx *c, double dt, const float *z, const float *pold, float *pnew,
                 float *y, double *part, const PcgScalars *sc, int first, const double *pb,
                 int npb, int iters) {
+  STS_PROF(c, "f32_pass_a");
   Args a{};
   a.out = pnew;
   a.y = y;
@@ -592,6 +600,7 @@ void f32_pass_a(const sts_ctx *c, double dt, const float *z, const float *pold, 
 
 void f32_residual(const sts_ctx *c, const double *b, const double *x, double dt, double *r,
                   double *part) {
+  STS_PROF(c, "f32_residual");
   Args a{};
   a.out = r;
   a.b = b;

@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <limits>
 #include <mutex>
 #include <string>
@@ -25,6 +27,7 @@ sts::Grid sts_ctx::grid() const {
   g.per2 = bc[4] == STS_BC_PERIODIC;
   g.dir_lo = bc[0] == STS_BC_DIRICHLET;
   g.dir_hi = bc[1] == STS_BC_DIRICHLET;
+  g.wg_rev = (debug & STS_DEBUG_WG_REVERSE) ? 1 : 0;
   g.t0 = d_t0;
   g.t1 = d_t1;
   g.t2 = d_t2;
@@ -153,6 +156,41 @@ static void *scratch_address(int device, std::string *err) {
 
 }  // namespace
 
+// ---- per-kernel timing ------------------------------------------------------
+
+namespace sts {
+
+constexpr size_t kProfMaxRecords = (size_t)1 << 20;
+
+static hipEvent_t prof_event(sts_ctx *c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(const sts_ctx *c, const char *name) {
+  if (!c || !c->profile || c->prof.size() >= kProfMaxRecords) return;
+  sts_ctx *m = const_cast<sts_ctx *>(c);
+  a_ = prof_event(m);
+  if (!a_ || hipEventRecord(a_, m->stream) != hipSuccess) return;
+  c_ = m;
+  name_ = name;
+}
+
+ProfScope::~ProfScope() {
+  if (!c_) return;
+  hipEvent_t b = prof_event(c_);
+  if (!b || hipEventRecord(b, c_->stream) != hipSuccess) return;
+  c_->prof.push_back(ProfRec{name_, a_, b});
+}
+
+}  // namespace sts
+
 extern "C" {
 
 sts_status sts_create(sts_ctx **out, int coord, int n0, int n1, int n2, const double *f0,
@@ -202,6 +240,10 @@ sts_status sts_create(sts_ctx **out, int coord, int n0, int n1, int n2, const do
     return STS_EHIP;
   }
   ctx->d_scratch = scratch_address(ctx->device, &ctx->scratch_err);
+  {
+    const char *e = std::getenv("STS_PROFILE");
+    ctx->profile = e && *e && std::strcmp(e, "0") != 0;
+  }
 
   // --- separable geometry tables ---
   std::vector<double> t0((size_t)NT0 * n0), t1((size_t)NT1 * n1), t2((size_t)NT2 * n2);
@@ -312,6 +354,11 @@ sts_status sts_destroy(sts_ctx *ctx) {
   dfree(ctx->d_red);
   dfree(ctx->d_sc);
   dfree(ctx->d_ilu);
+  for (auto &r : ctx->prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   dfree(ctx->d_gfac);
   dfree(ctx->d_pct);
   dfree(ctx->d_pcobj);
@@ -342,6 +389,59 @@ static sts_status refresh_dirichlet_values(sts_ctx *ctx) {
   for (int side = 0; side < 2; ++side)
     if (!ctx->ub_array[side]) launch_fill(ctx, ctx->d_bnd + (2 + side) * nb, nb, ctx->ub_const[side]);
   LAUNCHCHK();
+  return STS_OK;
+}
+
+sts_status sts_set_debug(sts_ctx *ctx, int flags) {
+  if (!ctx) return STS_EINVAL;
+  if (flags & ~STS_DEBUG_WG_REVERSE) FAIL(STS_EINVAL, "sts_set_debug: unknown flag");
+  ctx->debug = flags;
+  return STS_OK;
+}
+
+sts_status sts_set_profile(sts_ctx *ctx, int on) {
+  if (!ctx) return STS_EINVAL;
+  ctx->profile = on != 0;
+  return STS_OK;
+}
+
+sts_status sts_profile_summary(sts_ctx *ctx, char *buf, long long cap, int reset) {
+  if (!ctx || !buf || cap < 1) return STS_EINVAL;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  struct Agg {
+    long long n = 0;
+    double tot = 0.0, mn = 1e300, mx = 0.0;
+  };
+  std::map<std::string, Agg> agg;
+  for (const ProfRec &r : ctx->prof) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    Agg &a = agg[r.name];
+    a.n += 1;
+    a.tot += ms;
+    a.mn = std::min(a.mn, (double)ms);
+    a.mx = std::max(a.mx, (double)ms);
+  }
+  std::vector<std::pair<std::string, Agg>> rows(agg.begin(), agg.end());
+  std::sort(rows.begin(), rows.end(),
+            [](const auto &x, const auto &y) { return x.second.tot > y.second.tot; });
+  std::string out = "calls total_ms avg_us min_us max_us launcher\n";
+  char line[256];
+  for (const auto &r : rows) {
+    std::snprintf(line, sizeof line, "%lld %.4f %.2f %.2f %.2f %s\n", r.second.n, r.second.tot,
+                  1e3 * r.second.tot / r.second.n, 1e3 * r.second.mn, 1e3 * r.second.mx,
+                  r.first.c_str());
+    out += line;
+  }
+  if ((long long)out.size() + 1 > cap) FAIL(STS_EINVAL, "sts_profile_summary: buffer too small");
+  std::memcpy(buf, out.c_str(), out.size() + 1);
+  if (reset) {
+    for (const ProfRec &r : ctx->prof) {
+      ctx->prof_pool.push_back(r.a);
+      ctx->prof_pool.push_back(r.b);
+    }
+    ctx->prof.clear();
+  }
   return STS_OK;
 }
 

@@ -32,6 +32,7 @@ struct Grid {
   int n0, n1, n2;
   int per0, per1, per2;      // periodic flags
   int dir_lo, dir_hi;        // Dirichlet on axis-0 low / high side
+  int wg_rev;                // debug: workgroups take their work in reversed order
   const double *t0, *t1, *t2;  // tables: t0[tab * n0 + i] etc.
   double ab_lo, ab_hi, db_lo, db_hi;
 };
@@ -62,6 +63,31 @@ struct PcgScalars {
   int status;     // 0 ok, 1 converged, -4 breakdown
   int maxit;
 };
+
+// Per-kernel timing (STS_PROFILE, sts_set_profile): an event pair recorded
+// on the context's stream around each launcher's launch.
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+class ProfScope {
+ public:
+  ProfScope(const sts_ctx *c, const char *name);
+  ~ProfScope();
+  ProfScope(const ProfScope &) = delete;
+  ProfScope &operator=(const ProfScope &) = delete;
+
+ private:
+  sts_ctx *c_ = nullptr;
+  const char *name_ = nullptr;
+  hipEvent_t a_ = nullptr;
+};
+#define STS_PROF(c, name) ::sts::ProfScope sts_prof_scope_(c, name)
+
+// the workgroup's logical index (reversed in the debug order)
+__device__ __forceinline__ int wg_index(int rev) {
+  return rev ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+}
 
 }  // namespace sts
 
@@ -121,6 +147,11 @@ struct sts_ctx {
   double *d_rtab = nullptr;
   double *d_rws = nullptr;    // faces x 2, edges x 6 (PCG vectors)
   void *h_pin = nullptr;      // pinned host mirror of flags / scalars (two 128-byte slots)
+  int debug = 0;              // STS_DEBUG_* flags (sts_set_debug)
+  // per-kernel timing: records and a pool of reusable events
+  bool profile = false;
+  mutable std::vector<sts::ProfRec> prof;
+  mutable std::vector<hipEvent_t> prof_pool;
   hipEvent_t ev[2] = {nullptr, nullptr};  // PCG batch completion (pipelined polls)
 
   sts::Grid grid() const;

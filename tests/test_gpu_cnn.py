@@ -418,7 +418,7 @@ def test_errors_and_weights_roundtrip(gpu_lib):
     with pytest.raises(sts.StsError):
         net.conv(4, 0, x)
     with pytest.raises(sts.StsError):
-        net.conv(0, 5, x)
+        net.conv(0, 6, x)
 
 
 def test_moments(gpu_lib):

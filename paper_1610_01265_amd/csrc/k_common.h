@@ -55,6 +55,28 @@ __device__ __forceinline__ T stream_ld(const T *p) {
   if (STS_NT) return __builtin_nontemporal_load(p);
   return *p;
 }
+// Lane l of a wavefront receives v from lane l - 1 (DPP wave_shr:1, a
+// whole-wave shift); lane 0 receives lane0.  Every lane must be active.
+__device__ __forceinline__ float wave_shr1(float v, float lane0) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(lane0), __float_as_int(v),
+                                                    0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double wave_shr1(double v, double lane0) {
+  const unsigned long long a = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long o = (unsigned long long)__double_as_longlong(lane0);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)a,
+                                                            0x138, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32),
+                                                            (int)(unsigned)(a >> 32), 0x138, 0xf,
+                                                            0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// A load whose index is the same in every lane, through the scalar unit
+// (for data that no kernel writes while the launch runs).
+template <class T>
+__device__ __forceinline__ T uniform_ld(const T *p, int idx) {
+  return ((const __attribute__((address_space(4))) T *)p)[idx];
+}
 template <class T>
 __device__ __forceinline__ void stream_st(T *p, T v) {
   if (STS_NT)

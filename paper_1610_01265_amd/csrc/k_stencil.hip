@@ -39,6 +39,8 @@ namespace {
 // operands does not wait for the prefetch, which stays in flight across the
 // row.
 constexpr int TK = 64, TJ = STS_MARCH_TJ, NT = TK * TJ;
+// the in-sweep PCG reductions (block_sum_parts) assume 256-thread workgroups
+static_assert(NT == 256, "march workgroups must have 256 threads");
 constexpr int HK = TK + 2, HJ = TJ + 2, PL = HK * HJ;  // one LDS plane (tile + halo)
 constexpr int NLOAD = (PL + NT - 1) / NT;
 
@@ -105,6 +107,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   using R = typename Loader::value_type;
   if (MODE == M_PA && a.sc->done) return;
   __shared__ R s_u[4][PL];
+  __shared__ R s_cf[3][TJ][TK];  // w1, k01, k12 of the tile's rows (cross-lane modes)
   if constexpr (MODE == M_PA) {
     if (a.pb) {
       // the previous iteration's stopping test and this one's beta, from the
@@ -240,24 +243,54 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     if (MODE == M_DLAST) L.x1 = a.u0[cc];
     if (MODE == M_RES || MODE == M_RESN) L.x1 = a.b[cc];
   };
-  // same-plane neighbour coefficients of plane ip (loaded by neighbouring
-  // threads as their own: cache hits)
+  // Same-plane neighbour coefficients of plane ip.  Every one of them is
+  // some thread's own value.  In the stage modes they are passed between
+  // threads: the (k - 1) neighbours by a whole-wave DPP shift (a wavefront
+  // is 64 consecutive k of one row; lane 0 reads the column left of the
+  // tile through the scalar unit), the (j - 1) neighbours through LDS from
+  // the wavefront of the row above (the first row loads them).  This needs
+  // the own values first and a barrier; measured -8 % per RKL2 stage at
+  // 256 x 256 x 512, but +2 % per PCG pass A (non-temporal coefficient
+  // streams), which keeps the cached neighbour loads.
+  constexpr bool xlane = OP == OP_SPITZER && MODE != M_PA;
   auto load_nbr = [&](int ip, Loads &L) {
     if (OP == OP_SPITZER) {
       const int c = (ip * g.n1 + jc) * g.n2 + kc;
-      const int cB = c + tg.dJm, cC = c + tg.dKm;
-      L.w1B = R(C.w1[cB]);
-      L.k01B = R(C.k01[cB]);
-      L.k12B = R(C.k12[cB]);
-      L.w2C = R(C.w2[cC]);
-      L.k02C = R(C.k02[cC]);
-      L.k12C = R(C.k12[cC]);
-      L.k12BC = R(C.k12[cB + tg.dKm]);
+      const int cB = c + tg.dJm;
+      if constexpr (xlane) {
+        if (tj < TJ - 1) {
+          s_cf[0][tj][tk] = L.w1;
+          s_cf[1][tj][tk] = L.k01;
+          s_cf[2][tj][tk] = L.k12;
+        }
+        if (tj == 0) {
+          L.w1B = R(C.w1[cB]);
+          L.k01B = R(C.k01[cB]);
+          L.k12B = R(C.k12[cB]);
+        }
+        __syncthreads();
+        if (tj > 0) {
+          L.w1B = s_cf[0][tj - 1][tk];
+          L.k01B = s_cf[1][tj - 1][tk];
+          L.k12B = s_cf[2][tj - 1][tk];
+        }
+        const int cC0 = __builtin_amdgcn_readfirstlane(c + tg.dKm);
+        const int cBC0 = __builtin_amdgcn_readfirstlane(cB + tg.dKm);
+        L.w2C = wave_shr1(L.w2, R(uniform_ld(C.w2, cC0)));
+        L.k02C = wave_shr1(L.k02, R(uniform_ld(C.k02, cC0)));
+        L.k12C = wave_shr1(L.k12, R(uniform_ld(C.k12, cC0)));
+        L.k12BC = wave_shr1(L.k12B, R(uniform_ld(C.k12, cBC0)));
+      } else {
+        const int cC = c + tg.dKm;
+        L.w1B = R(C.w1[cB]);
+        L.k01B = R(C.k01[cB]);
+        L.k12B = R(C.k12[cB]);
+        L.w2C = R(C.w2[cC]);
+        L.k02C = R(C.k02[cC]);
+        L.k12C = R(C.k12[cC]);
+        L.k12BC = R(C.k12[cB + tg.dKm]);
+      }
     }
-  };
-  auto load_plane_cells = [&](int ip, Loads &L) {
-    load_own(ip, L);
-    load_nbr(ip, L);
   };
   // Conduction: the part of the row of the cell of plane i that the faces and
   // edges joining planes i - 1 and i contribute, evaluated with plane i - 1
@@ -293,8 +326,10 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
 
   for (int i = i0; i < i1; ++i) {
     const bool pre = i + 2 <= i1;
-    load_plane_cells(i, cur);
+    load_own(i, cur);
+    if (!xlane) load_nbr(i, cur);
     load_plane(i + 2, v);  // clamped / wrapped plane index: always in the grid
+    if (xlane) load_nbr(i, cur);  // waits for the own values and the other rows
     // The RKL2 stage output is stored after the LDS ring update below: the
     // vector-memory counter also counts stores, so a store issued before the
     // update would make its wait for the prefetched plane wait for the store

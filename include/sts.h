@@ -76,8 +76,13 @@ long long sts_num_cells(const sts_ctx *ctx);
  * factor kernels take their work in reversed workgroup order (each
  * workgroup still computes the same tiles and partial sums), a self-check
  * that results do not depend on the order in which workgroups run: results
- * are bit for bit those of the normal order.  */
-enum { STS_DEBUG_WG_REVERSE = 1 };
+ * are bit for bit those of the normal order.  STS_DEBUG_SEPARATE_FINALIZE
+ * makes the Jacobi and factor PCG evaluate alpha, beta and the stopping
+ * test in single-workgroup kernels between the sweeps instead of inside
+ * them (the same sums in the same order: bit for bit the same iterates), for
+ * timing the two forms; without it the in-sweep form is taken up to 4096
+ * workgroups of the plane march (beyond, the separate one).  */
+enum { STS_DEBUG_WG_REVERSE = 1, STS_DEBUG_SEPARATE_FINALIZE = 2 };
 sts_status sts_set_profile(sts_ctx *ctx, int on);
 sts_status sts_profile_summary(sts_ctx *ctx, char *buf, long long cap, int reset);
 sts_status sts_set_debug(sts_ctx *ctx, int flags);

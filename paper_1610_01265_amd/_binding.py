@@ -17,6 +17,7 @@ SPHERICAL, CARTESIAN = 0, 1
 BC_ZEROFLUX, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 PC_JACOBI, PC_BLOCK_ILU0, PC_FACTOR = 0, 1, 2
 DEBUG_WG_REVERSE = 1
+DEBUG_SEPARATE_FINALIZE = 2
 SHELL_BC = (BC_DIRICHLET, BC_ZEROFLUX, BC_ZEROFLUX, BC_ZEROFLUX, BC_PERIODIC, BC_PERIODIC)
 
 _STATUS = {0: "STS_OK", 1: "STS_NOT_CONVERGED", -1: "STS_EINVAL", -2: "STS_EHIP",

@@ -78,30 +78,19 @@ __global__ void __launch_bounds__(NT)
   });
 }
 
-// z = G t; DOTS: partial sums r.z (region 0) and r.r (region cap)
-template <bool DOTS>
+// z = G t
 __global__ void __launch_bounds__(NT)
     k_pc_g(PcDims d, const float *__restrict__ g, const double *__restrict__ t,
-           double *__restrict__ z, const double *__restrict__ r, double *part, long long cap,
-           const PcgScalars *sc) {
+           double *__restrict__ z, const PcgScalars *sc) {
   if (sc && sc->done) return;
   const float *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
-  double rz = 0.0, rr = 0.0;
   for_cells(d, [&](int i, int j, int k, long long c) {
     double v = (double)g[c] * t[c];
     if (i > 0) v += (double)g1[c] * t[c - d.n12];
     if (j > 0) v += (double)g2[c] * t[c - d.n2];
     if (k > 0) v += (double)g3[c] * t[c - 1];
     z[c] = v;
-    if (DOTS) {
-      const double rv = r[c];
-      rz += rv * v;
-      rr += rv * rv;
-    }
   });
-  if (DOTS)
-    wg_sum2<NT>(rz, rr, threadIdx.y * TX + threadIdx.x, part + wg_index(d.rev),
-                part + cap + wg_index(d.rev));
 }
 
 // 1 / sqrt(A_cc), A_cc = V - dt S_cc
@@ -215,20 +204,43 @@ __global__ void __launch_bounds__(NT)
   wg_sum2<NT>(rr, 0.0, threadIdx.y * TX + threadIdx.x, part + wg_index(d.rev), nullptr);
 }
 
-// x += alpha p, r -= alpha y (alpha from the finalizer); no preconditioner
-// and no dots: those follow in k_pc_gt / k_pc_g<true>
+// The x / r update of a factor-PCG iteration fused with t = G^T r_new:
+// x += alpha p, r_out = r_in - alpha y, t = G^T r_out.  A cell's t needs
+// r_new of its +e_a neighbours, formed here from r_in and y exactly as their
+// owners form it (the same operations: the same bits), so r_in and r_out
+// are different arrays.  Partial sums: t.t (= r.z for z = G t, which
+// k_pc_g forms next) and r.r.  FUSE: alpha from pass A's partials pa[0..npa)
+// in every workgroup (pcg_alpha), workgroup 0 recording it.
+template <bool FUSE>
 __global__ void __launch_bounds__(NT)
-    k_pass_b_xr(long long n, double *__restrict__ x, const double *__restrict__ p,
-                double *__restrict__ r, const double *__restrict__ y, const PcgScalars *sc,
-                int rev) {
+    k_pc_xr_gt(PcDims d, const float *__restrict__ g, double *__restrict__ x,
+               const double *__restrict__ p, const double *__restrict__ rin,
+               double *__restrict__ rout, const double *__restrict__ y, double *__restrict__ t,
+               double *part, long long cap, PcgScalars *sc, const double *pa, int npa) {
   if (sc->done) return;
-  const double alpha = sc->alpha;
-  const long long stride = (long long)gridDim.x * NT;
-  for (long long c = (long long)wg_index(rev) * NT + threadIdx.y * TX + threadIdx.x; c < n;
-       c += stride) {
-    x[c] = x[c] + alpha * p[c];
-    r[c] = r[c] - alpha * y[c];
+  const int tid = threadIdx.y * TX + threadIdx.x;
+  double alpha;
+  if (FUSE) {
+    if (!pcg_alpha(pa, npa, sc, blockIdx.x == 0, tid, &alpha)) return;
+  } else {
+    alpha = sc->alpha;
   }
+  const float *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
+  double tt = 0.0, rr = 0.0;
+  for_cells(d, [&](int i, int j, int k, long long c) {
+    const double rn = rin[c] - alpha * y[c];
+    x[c] = x[c] + alpha * p[c];
+    rout[c] = rn;
+    double v = (double)g[c] * rn;
+    if (i + 1 < d.n0) v += (double)g1[c + d.n12] * (rin[c + d.n12] - alpha * y[c + d.n12]);
+    if (j + 1 < d.n1) v += (double)g2[c + d.n2] * (rin[c + d.n2] - alpha * y[c + d.n2]);
+    if (k + 1 < d.n2) v += (double)g3[c + 1] * (rin[c + 1] - alpha * y[c + 1]);
+    t[c] = v;
+    tt += v * v;
+    rr += rn * rn;
+  });
+  const int w = wg_index(d.rev);
+  wg_sum2<NT>(tt, rr, tid, part + w, part + cap + w);
 }
 
 int grid_items(const PcDims &d) { return (int)(d.items < 2048 ? d.items : 2048); }
@@ -245,16 +257,11 @@ void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const doubl
                      sc);
 }
 
-void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z, const double *r,
-                 double *part, const PcgScalars *sc) {
+void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z,
+                 const PcgScalars *sc) {
   STS_PROF(c, "launch_pc_g");
   const PcDims d = dims_of(c);
-  if (r)
-    hipLaunchKernelGGL(k_pc_g<true>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, t,
-                       z, r, part, (long long)c->red_cap, sc);
-  else
-    hipLaunchKernelGGL(k_pc_g<false>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, t,
-                       z, nullptr, nullptr, 0LL, sc);
+  hipLaunchKernelGGL(k_pc_g, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, t, z, sc);
 }
 
 void launch_pc_build(const sts_ctx *c, double dt, const float *o4, float *g, int *bad) {
@@ -287,13 +294,19 @@ void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y
                      (const double *)c->d_sdiag, dt, g, y, r, s, z, dg, (__bf16 *)dout, part);
 }
 
-void launch_pass_b_xr(const sts_ctx *c, double *x, const double *p, double *r, const double *y,
-                      const PcgScalars *sc) {
-  STS_PROF(c, "launch_pass_b_xr");
-  const long long n = c->ncell;
-  const long long nb = (n + NT - 1) / NT;
-  hipLaunchKernelGGL(k_pass_b_xr, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(TX, TY), 0,
-                     c->stream, n, x, p, r, y, sc, (c->debug & STS_DEBUG_WG_REVERSE) ? 1 : 0);
+void launch_pc_xr_gt(const sts_ctx *c, const float *g, double *x, const double *p,
+                     const double *rin, double *rout, const double *y, double *t, double *part,
+                     PcgScalars *sc, const double *pa, int npa) {
+  STS_PROF(c, "launch_pc_xr_gt");
+  const PcDims d = dims_of(c);
+  if (pa)
+    hipLaunchKernelGGL(k_pc_xr_gt<true>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g,
+                       x, p, rin, rout, y, t, part, (long long)c->red_cap, sc, pa, npa);
+  else
+    hipLaunchKernelGGL(k_pc_xr_gt<false>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d,
+                       g, x, p, rin, rout, y, t, part, (long long)c->red_cap, sc,
+                       (const double *)nullptr, 0);
 }
+
 
 }  // namespace sts

@@ -336,6 +336,15 @@ void launch_pass_b_jacobi_fused(const sts_ctx *c, double *x, const double *p, do
                      x, p, r, y, invd, z, part, cap_of(c), sc, pa, npa, rev_of(c));
 }
 
+void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
+                          const double *y, const double *invd, double *z, double *part,
+                          PcgScalars *sc) {
+  STS_PROF(c, "launch_pass_b_jacobi");
+  hipLaunchKernelGGL(k_pass_b_jac<false>, dim3(pass_b_parts(c)), dim3(NT), 0, c->stream,
+                     c->ncell, x, p, r, y, invd, z, part, cap_of(c), sc, (const double *)nullptr,
+                     0, rev_of(c));
+}
+
 void launch_finalize_check(const sts_ctx *c, const double *part, int nparts, int iters,
                            PcgScalars *sc) {
   STS_PROF(c, "launch_finalize_check");

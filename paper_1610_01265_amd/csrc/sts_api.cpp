@@ -394,7 +394,8 @@ static sts_status refresh_dirichlet_values(sts_ctx *ctx) {
 
 sts_status sts_set_debug(sts_ctx *ctx, int flags) {
   if (!ctx) return STS_EINVAL;
-  if (flags & ~STS_DEBUG_WG_REVERSE) FAIL(STS_EINVAL, "sts_set_debug: unknown flag");
+  if (flags & ~(STS_DEBUG_WG_REVERSE | STS_DEBUG_SEPARATE_FINALIZE))
+    FAIL(STS_EINVAL, "sts_set_debug: unknown flag");
   ctx->debug = flags;
   return STS_OK;
 }
@@ -978,15 +979,24 @@ static sts_status be_pcg_solve_f32(sts_ctx *ctx, const double *u_n, double *x, d
     HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     float *pold = p0, *pnew = p1;
-    // the finalizers run inside the sweeps, as in the FP64 Jacobi solve
+    // the finalizers run inside the sweeps up to kFuseMaxParts pass-A
+    // partials, as in the FP64 Jacobi solve
     double *part_b = part + 2 * cap;
+    const bool fuse = fuse_finalizers(ctx, np3);
     st = pcg_iterate(ctx, sc, maxit - total, [&](int it) {
-      f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, np1, it);
-      f32_pass_b(ctx, e, pnew, r, y, iv, z, part_b, sc, part, np3);
+      if (fuse) {
+        f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, np1, it);
+        f32_pass_b(ctx, e, pnew, r, y, iv, z, part_b, sc, part, np3);
+      } else {
+        f32_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
+        launch_finalize_alpha(ctx, part, np3, sc);
+        f32_pass_b(ctx, e, pnew, r, y, iv, z, part_b, sc);
+        launch_finalize_beta(ctx, part_b, np1, sc);
+      }
       std::swap(pold, pnew);
     });
     if (st) return st;
-    if (maxit - total > 0 && !h->done) {
+    if (fuse && maxit - total > 0 && !h->done) {
       launch_finalize_check(ctx, part_b, np1, maxit - total, sc);
       LAUNCHCHK();
       HIPCHK(hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
@@ -1054,7 +1064,7 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   }
   if (fpc) {  // z = G (G^T r)
     launch_pc_gt(ctx, ctx->d_gfac, r, nullptr, ctx->d_pct, nullptr);
-    launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, nullptr, nullptr, nullptr);
+    launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, nullptr);
     LAUNCHCHK();
   }
   // every preconditioner keeps z in its own array: pass A forms p = z + beta p
@@ -1076,8 +1086,13 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
   // evaluates the stopping test and beta from those, so no kernel sits
   // between the sweeps (-4 to -5 % per solve, conduction and viscosity).
   // Block ILU0 keeps the separate finalizers (fused, its latency-bound solve
-  // sweep measured no faster).
+  // sweep measured no faster).  Beyond kFuseMaxParts pass-A partials, and
+  // with STS_DEBUG_SEPARATE_FINALIZE, Jacobi takes the four-launch form
+  // (single-workgroup finalizers) as well.
   double *part_b = part + 2 * cap;
+  const bool fuse = fuse_finalizers(ctx, np3);
+  // the factor's second residual array: 1 / A_ii is not used after the start
+  double *rcur = r, *ralt = invd;
   st = pcg_iterate(ctx, sc, maxit, [&](int it) {
     if (ilu) {
       launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
@@ -1085,21 +1100,35 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
       launch_pass_b_ilu(ctx, blk, fac, x, pnew, r, y, z, part, sc);
       launch_finalize_beta(ctx, part, nb_parts, sc);
     } else if (fpc) {
-      // pass B updates x and r; z = G (G^T r) and the dots r.z, r.r follow
-      launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
-      launch_finalize_alpha(ctx, part, np3, sc);
-      launch_pass_b_xr(ctx, x, pnew, r, y, sc);
-      launch_pc_gt(ctx, ctx->d_gfac, r, nullptr, ctx->d_pct, sc);
-      launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, r, part, sc);
-      launch_finalize_beta(ctx, part, nb_parts, sc);
-    } else {
+      // pass B updates x and r and forms t = G^T r (r ping-pongs between two
+      // arrays: the sweep reads its neighbours' old r), with r.z = t.t;
+      // z = G t follows.  The finalizers run inside the sweeps as for Jacobi.
+      if (fuse) {
+        launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, nb_parts, it);
+        launch_pc_xr_gt(ctx, ctx->d_gfac, x, pnew, rcur, ralt, y, ctx->d_pct, part_b, sc, part,
+                        np3);
+      } else {
+        launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
+        launch_finalize_alpha(ctx, part, np3, sc);
+        launch_pc_xr_gt(ctx, ctx->d_gfac, x, pnew, rcur, ralt, y, ctx->d_pct, part_b, sc,
+                        nullptr, 0);
+        launch_finalize_beta(ctx, part_b, nb_parts, sc);
+      }
+      launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, sc);
+      std::swap(rcur, ralt);
+    } else if (fuse) {
       launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0, part_b, nb_parts, it);
       launch_pass_b_jacobi_fused(ctx, x, pnew, r, y, invd, z, part_b, sc, part, np3);
+    } else {
+      launch_pass_a(ctx, dt, z, pold, pnew, y, part, sc, it == 0);
+      launch_finalize_alpha(ctx, part, np3, sc);
+      launch_pass_b_jacobi(ctx, x, pnew, r, y, invd, z, part_b, sc);
+      launch_finalize_beta(ctx, part_b, nb_parts, sc);
     }
     std::swap(pold, pnew);
   });
   if (st) return st;
-  if (!ilu && !fpc && maxit > 0 && !h->done) {
+  if (!ilu && fuse && maxit > 0 && !h->done) {
     // every one of the maxit iterations ran; evaluate the last one's end
     launch_finalize_check(ctx, part_b, nb_parts, maxit, sc);
     LAUNCHCHK();
@@ -1167,7 +1196,7 @@ sts_status sts_apply_pc_factor(sts_ctx *ctx, const double *r, double *z) {
   sts_status st;
   if (!ctx->d_pct && (st = dalloc(ctx, (void **)&ctx->d_pct, (size_t)ctx->ncell * 8))) return st;
   launch_pc_gt(ctx, ctx->d_gfac, r, nullptr, ctx->d_pct, nullptr);
-  launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, nullptr, nullptr, nullptr);
+  launch_pc_g(ctx, ctx->d_gfac, ctx->d_pct, z, nullptr);
   LAUNCHCHK();
   return STS_OK;
 }
@@ -1196,10 +1225,10 @@ sts_status sts::pc_objective_sweeps(sts_ctx *ctx, double dt, const double *z, do
          *p = w + 5 * n;
   double *part = ctx->d_red;
   const float *g = ctx->d_gfac;
-  launch_pc_g(ctx, g, z, w, nullptr, nullptr, nullptr);
+  launch_pc_g(ctx, g, z, w, nullptr);
   launch_pass_a(ctx, dt, w, nullptr, p, y, part, ctx->d_sc0, 1);
   launch_pc_gt(ctx, g, y, z, r, nullptr);
-  launch_pc_g(ctx, g, r, q, nullptr, nullptr, nullptr);
+  launch_pc_g(ctx, g, r, q, nullptr);
   launch_pass_a(ctx, dt, q, nullptr, p, s, part, ctx->d_sc0, 1);
   launch_pc_grad(ctx, dt, g, y, r, s, z, dg, dout, part);
   LAUNCHCHK();

@@ -262,8 +262,21 @@ void launch_finalize_beta(const sts_ctx *c, const double *part, int nparts, PcgS
 void launch_pass_b_jacobi_fused(const sts_ctx *c, double *x, const double *p, double *r,
                                 const double *y, const double *invd, double *z, double *part,
                                 PcgScalars *sc, const double *pa, int npa);
+// the same sweep with alpha from sc (written by launch_finalize_alpha)
+void launch_pass_b_jacobi(const sts_ctx *c, double *x, const double *p, double *r,
+                          const double *y, const double *invd, double *z, double *part,
+                          PcgScalars *sc);
 void launch_finalize_check(const sts_ctx *c, const double *part, int nparts, int iters,
                            PcgScalars *sc);
+// In-sweep finalizers: every pass-B workgroup re-sums pass A's partials and
+// every pass-A workgroup pass B's, a cost that grows with the product of the
+// two workgroup counts.  Measured per Jacobi iteration: fused 4-5 % faster at
+// 128 x 128 x 256 (1024 pass-A workgroups), separate 0.7 % faster at
+// 256 x 256 x 512 (8192) and 0.8 % at 1023 x 1024 x 1024 (262144).
+constexpr int kFuseMaxParts = 4096;
+inline bool fuse_finalizers(const sts_ctx *c, int pass_a_parts) {
+  return !(c->debug & STS_DEBUG_SEPARATE_FINALIZE) && pass_a_parts <= kFuseMaxParts;
+}
 void launch_true_residual(const sts_ctx *c, const double *b, const double *x, double dt,
                           double *part);
 void launch_sum2(const sts_ctx *c, const double *part, int nparts, double *out2);
@@ -286,9 +299,9 @@ int pc_parts(const sts_ctx *c);  // workgroups (partials) of the pc kernels
 // t = G^T x (- sub, may be null); sc (may be null): no-op once sc->done
 void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const double *sub,
                   double *t, const PcgScalars *sc);
-// z = G t; r != null: partial sums r.z, r.r into part, part + red_cap
-void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z, const double *r,
-                 double *part, const PcgScalars *sc);
+// z = G t; sc (may be null): no-op once sc->done
+void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z,
+                 const PcgScalars *sc);
 // factor from network outputs o4 [cells][4] (null: point Jacobi) at dt
 void launch_pc_build(const sts_ctx *c, double dt, const float *o4, float *g, int *bad);
 void launch_pc_check(const sts_ctx *c, const float *g, int *bad);
@@ -297,8 +310,12 @@ void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T,
 void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y,
                     const double *r, const double *s, const double *z, double *dg, void *dout,
                     double *part);
-void launch_pass_b_xr(const sts_ctx *c, double *x, const double *p, double *r, const double *y,
-                      const PcgScalars *sc);
+// x += alpha p, r_out = r_in - alpha y, t = G^T r_out (r_in != r_out); partial
+// sums t.t and r.r to part, part + cap; pa != null: alpha from pass A's
+// partials pa (npa) inside the sweep, else from sc
+void launch_pc_xr_gt(const sts_ctx *c, const float *g, double *x, const double *p,
+                     const double *rin, double *rout, const double *y, double *t, double *part,
+                     PcgScalars *sc, const double *pa, int npa);
 // host helpers of the factor network (sts_api.cpp): the factor built from
 // network outputs o4 [cells][4] at dt (STS_BREAKDOWN if an entry is not
 // finite), and the objective's sweeps at dt for probe z, writing dL/dG (dg)

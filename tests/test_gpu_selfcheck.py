@@ -100,3 +100,51 @@ def test_profile_counts_launches(gpu_lib):
     ctx.apply_F(T)
     assert ctx.profile_summary() == {}
     ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 130), (64, 64, 128)])
+def test_separate_finalizers_match_fused(gpu_lib, shape):
+    """The Jacobi and factor PCG with alpha, beta and the stopping test in
+    kernels of their own sum the same partials in the same order as the
+    in-sweep form: the same iterations, residual and solution bit for bit,
+    converged or stopped at maxit (FP64 and the FP32 form)."""
+    import torch
+    sts = gpu_lib
+    w = small_shell(shape, seed=5)
+    res = []
+    for flags in (0, sts.DEBUG_SEPARATE_FINALIZE):
+        ctx = gpu_spitzer(sts, w["rf"], w["thf"], w["phf"], w["T"], w["br"], w["bt"], w["bp"],
+                          w["kappa0"], BC, u_lo=w["T_inner"])
+        ctx.set_debug(flags)
+        T = _cuda(w["T"])
+        dt = 120.0 * ctx.dt_euler()
+        out = []
+        for maxit in (10000, 7):
+            x = T.clone()
+            it, rel, st = ctx.be_pcg_solve(T, x, dt, rtol=1e-10, maxit=maxit,
+                                           allow_not_converged=True)
+            out.append((it, rel, st, _host(x)))
+        # the factored preconditioner's solve (a seeded factor)
+        rng = np.random.default_rng(4)
+        g = np.zeros((4,) + shape, np.float32)
+        g[0] = 1e-3 * (1.0 + 0.1 * rng.random(shape))
+        g[1:] = 1e-4 * rng.standard_normal((3,) + shape)
+        ctx.set_pc_factor(_cuda(g))
+        for maxit in (10000, 5):
+            x = T.clone()
+            it, rel, st = ctx.be_pcg_solve(T, x, dt, pc=sts.PC_FACTOR, rtol=1e-10, maxit=maxit,
+                                           allow_not_converged=True)
+            out.append((it, rel, st, _host(x)))
+        # the FP32 form's inner Jacobi solve
+        f = torch.float32
+        ctx.set_spitzer_f32(T.to(f), w["kappa0"], *[_cuda(w[k]).to(f) for k in ("br", "bt", "bp")])
+        x = T.clone()
+        it, rel, st = ctx.be_pcg_solve(T, x, dt, rtol=1e-8)
+        out.append((it, rel, st, _host(x)))
+        res.append(out)
+        ctx.close()
+    for a, b in zip(*res):
+        assert a[:3] == b[:3]
+        assert np.array_equal(a[3], b[3])
+    assert res[0][1][0] == 7 and res[0][1][2] != 0
+    assert res[0][3][0] == 5 and res[0][3][2] != 0

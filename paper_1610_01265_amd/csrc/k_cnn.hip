@@ -209,33 +209,46 @@ __global__ void __launch_bounds__(256)
 //   db[co]          = sum_cells dout[cell][co]
 // As an MFMA product with K = cells: A = dout (lane: co = l%16, 8 cells),
 // B = act shifted by the tap (lane: ci = l%16, the same 8 cells), C[co][ci];
-// the bias is a 28th product with B = ones.  Workgroups march r-planes of a
-// 4 x 64 tile like the convolution (3-plane LDS ring of the input window,
-// the tile of dout staged per plane) and accumulate all 28 products in
-// registers over the work items they take (grid-stride); each workgroup
-// writes its partial sums, reduced in a fixed order by k_wgrad_reduce.
-// LDS cells are 32 B (16 channels) with a 32-B gap after every 8 cells, so
-// the 2-byte operand reads of the four 16-lane groups fall in disjoint banks.
+// the bias is a 28th product with B = ones.  Workgroups take work items
+// (a 4 x 64 tile and a chunk of r-planes, grid-stride) and march the
+// activation planes p of the chunk and its two halo planes: act plane p is
+// the tap-a operand of output plane x = p - a, so each B fragment gathered
+// from LDS feeds the products of the three output planes p + 1, p, p - 1
+// (a = -1, 0, +1), whose dout fragments stay in registers; every (x, tap)
+// pair meets once.  The activation plane and the dout tile are double
+// buffered in LDS (one barrier per plane); all 28 products accumulate in
+// registers, and each workgroup writes its partial sums, reduced in a fixed
+// order by k_wgrad_reduce.  LDS cells are 32 B (16 channels) with a 32-B
+// gap after every 8 cells, so the 2-byte operand reads of the four 16-lane
+// groups fall in disjoint banks.
 __device__ __forceinline__ int lds_cell(int x) { return (x + (x >> 3)) * CC; }
 
 constexpr int PLCP = PLC + (PLC + 7) / 8;        // padded cells of one ring plane
 constexpr int TCP = TJC * TKC + TJC * TKC / 8;   // padded cells of the dout tile
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
     k_wgrad(CnnGrid g, const __bf16 *__restrict__ act, const __bf16 *__restrict__ dout,
             float *__restrict__ part, int CI, int nitems) {
-  __shared__ __attribute__((aligned(16))) __bf16 s_in[3][PLCP * CC];
-  __shared__ __attribute__((aligned(16))) __bf16 s_d[TCP * CC];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  __shared__ __attribute__((aligned(16))) __bf16 s_in[2][PLCP * CC];
+  __shared__ __attribute__((aligned(16))) __bf16 s_d[2][TCP * CC];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int grp = lane >> 4, cl = lane & 15;
+  // operand reads: cell u + 8 grp + e of a padded plane sits at
+  // lds_cell(u + e) + 9 grp CC (u a multiple of 8 plus a wave-uniform
+  // shift), so every read is one per-lane base plus a uniform offset
+  const int lane_off = grp * 9 * CC + cl;
   const int ntk = (g.n2 + TKC - 1) / TKC, ntj = (g.n1 + TJC - 1) / TJC;
   const long long n12 = (long long)g.n1 * g.n2;
   f32x4 acc[NTAP + 1];
 #pragma unroll
   for (int q = 0; q <= NTAP; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bf16x8 ones;
+  bf16x8 ones, zero8;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+  for (int e = 0; e < 8; ++e) {
+    ones[e] = (__bf16)1.0f;
+    zero8[e] = (__bf16)0.0f;
+  }
   constexpr int NCH = PLC * 2;
   constexpr int NLD = (NCH + 255) / 256;
 
@@ -260,60 +273,100 @@ __global__ void __launch_bounds__(256)
     const int dj = t >> 6, dk = t & 63;
     const bool din = j0 + dj < g.n1 && k0 + dk < g.n2;
     const int doff = ((j0 + dj) * g.n2 + (k0 + dk)) * 2;
-    auto load_plane = [&](int ip, u32x4 *v) {
+    auto load_act = [&](int ip, u32x4 *v) {
       const bool pin = ip >= 0 && ip < g.n0;
-      const u32x4 *base = reinterpret_cast<const u32x4 *>(act + (long long)(pin ? ip : 0) * n12 * CC);
+      const u32x4 *base =
+          reinterpret_cast<const u32x4 *>(act + (long long)(pin ? ip : 0) * n12 * CC);
 #pragma unroll
-      for (int q = 0; q < NLD; ++q) {
-        v[q] = (pin && src[q] >= 0) ? base[src[q]] : u32x4(0u);
-      }
+      for (int q = 0; q < NLD; ++q) v[q] = (pin && src[q] >= 0) ? base[src[q]] : u32x4(0u);
     };
-    auto store_plane = [&](int ip, const u32x4 *v) {
-      u32x4 *sp = reinterpret_cast<u32x4 *>(s_in[(ip + 3) % 3]);
+    auto store_act = [&](int ip, const u32x4 *v) {
+      u32x4 *sp = reinterpret_cast<u32x4 *>(s_in[ip & 1]);
 #pragma unroll
       for (int q = 0; q < NLD; ++q)
         if (dst[q] >= 0) sp[dst[q]] = v[q];
     };
-    u32x4 v[NLD];
-    __syncthreads();  // the previous item's reads of the ring are done
-    load_plane(i0 - 1, v);
-    store_plane(i0 - 1, v);
-    load_plane(i0, v);
-    store_plane(i0, v);
-    load_plane(i0 + 1, v);
-    store_plane(i0 + 1, v);
-    for (int i = i0; i < i1; ++i) {
-      const bool pre = i + 2 <= i1;
-      if (pre) load_plane(i + 2, v);
-      u32x4 d0 = u32x4(0u), d1 = u32x4(0u);
-      if (din) {
-        const u32x4 *dp = reinterpret_cast<const u32x4 *>(dout + (long long)i * n12 * CC);
-        d0 = dp[doff];
-        d1 = dp[doff + 1];
+    auto load_dout = [&](int ip, u32x4 *d) {
+      d[0] = d[1] = u32x4(0u);
+      if (din && ip < i1) {
+        const u32x4 *dp = reinterpret_cast<const u32x4 *>(dout + (long long)ip * n12 * CC);
+        d[0] = dp[doff];
+        d[1] = dp[doff + 1];
       }
-      u32x4 *sd = reinterpret_cast<u32x4 *>(s_d);
-      sd[lds_cell(t) / 8] = d0;
-      sd[lds_cell(t) / 8 + 1] = d1;
+    };
+    auto store_dout = [&](int ip, const u32x4 *d) {
+      u32x4 *sd = reinterpret_cast<u32x4 *>(s_d[ip & 1]);
+      sd[lds_cell(t) / 8] = d[0];
+      sd[lds_cell(t) / 8 + 1] = d[1];
+    };
+    // A fragments of output plane x (its dout tile staged in s_d[x & 1])
+    auto gather_a = [&](int x, bf16x8 *a) {
+      const __bf16 *sd = s_d[x & 1] + lane_off;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int u = wv * TKC + ks * 32;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[ks][e] = sd[lds_cell(u + e)];
+      }
+    };
+    // act plane p + 1 and dout plane p + 2 are staged while plane p is used
+    __syncthreads();  // the previous item's reads of the buffers are done
+    {
+      u32x4 v[NLD], d[2];
+      load_act(i0 - 1, v);
+      load_dout(i0, d);
+      store_act(i0 - 1, v);
+      store_dout(i0, d);
+    }
+    __syncthreads();
+    bf16x8 am[2] = {zero8, zero8}, a0[2] = {zero8, zero8}, ap[2];
+    for (int p = i0 - 1; p <= i1; ++p) {
+      // dout of output plane p + 1 (zero outside the chunk)
+      if (p + 1 < i1) {
+        gather_a(p + 1, ap);
+      } else {
+        ap[0] = ap[1] = zero8;
+      }
+      u32x4 v[NLD], d[2];
+      const bool nxt_act = p + 1 <= i1, nxt_d = p + 2 < i1;
+      if (nxt_act) load_act(p + 1, v);
+      if (nxt_d) load_dout(p + 2, d);
+      if (p >= 0 && p < g.n0) {
+        const __bf16 *pl = s_in[p & 1] + lane_off;
+        // B fragment q = 9 ks + bc of this plane: (b, c) = (bc / 3 - 1, bc % 3 - 1)
+        auto gather_b = [&](int q, bf16x8 &bv) {
+          const int ks = q / 9, bc = q % 9;
+          const int u = (wv + 1 + bc / 3 - 1) * HKC + bc % 3 + ks * 32;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bv[e] = pl[lds_cell(u + e)];
+        };
+        // software pipeline: fragment q + 1 is read while q's products issue
+        bf16x8 bq[2];
+        gather_b(0, bq[0]);
+#pragma unroll
+        for (int q = 0; q < 18; ++q) {
+          const int ks = q / 9, bc = q % 9;
+          if (q + 1 < 18) gather_b(q + 1, bq[(q + 1) & 1]);
+          __builtin_amdgcn_sched_barrier(0);
+          const bf16x8 bv = bq[q & 1];
+          // tap (a, b, c) = 9 (a + 1) + 3 (b + 1) + (c + 1); output plane p - a
+          // (a zero fragment outside the chunk adds exact zeros)
+          acc[18 + bc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[ks], bv, acc[18 + bc], 0, 0, 0);
+          acc[9 + bc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[ks], bv, acc[9 + bc], 0, 0, 0);
+          acc[bc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[ks], bv, acc[bc], 0, 0, 0);
+          if (bc == 0)
+            acc[NTAP] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[ks], ones, acc[NTAP], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if (nxt_act) store_act(p + 1, v);
+      if (nxt_d) store_dout(p + 2, d);
       __syncthreads();
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        bf16x8 av;
-        const int c0 = wv * TKC + ks * 32 + grp * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = s_d[lds_cell(c0 + e) + cl];
-        acc[NTAP] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, acc[NTAP], 0, 0, 0);
-#pragma unroll
-        for (int tap = 0; tap < NTAP; ++tap) {
-          const __bf16 *pl = s_in[(i + tap_a(tap) + 3) % 3];
-          const int h0 = (wv + 1 + tap_b(tap)) * HKC + 1 + tap_c(tap) + ks * 32 + grp * 8;
-          bf16x8 bv;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) bv[e] = pl[lds_cell(h0 + e) + cl];
-          acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tap], 0, 0, 0);
-        }
+        am[ks] = a0[ks];
+        a0[ks] = ap[ks];
       }
-      __syncthreads();
-      if (pre) store_plane(i + 2, v);
     }
   }
   // sum the four wavefronts in a fixed order (ring memory reused)

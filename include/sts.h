@@ -72,8 +72,9 @@ long long sts_num_cells(const sts_ctx *ctx);
  * line per launcher, "calls total_ms avg_us min_us max_us name", by total
  * time; reset != 0 clears the records.  STS_EINVAL if buf is too small.
  * Synchronises the stream.
- * sts_set_debug - flags; STS_DEBUG_WG_REVERSE makes the stencil, PCG and
- * factor kernels take their work in reversed workgroup order (each
+ * sts_set_debug - flags; STS_DEBUG_WG_REVERSE makes the stencil, PCG,
+ * block-ILU0, factor, CNN and resistivity kernels that use LDS or write
+ * per-workgroup partial sums take their work in reversed workgroup order (each
  * workgroup still computes the same tiles and partial sums), a self-check
  * that results do not depend on the order in which workgroups run: results
  * are bit for bit those of the normal order.  STS_DEBUG_SEPARATE_FINALIZE

@@ -9,7 +9,10 @@
 
 using namespace sts;
 
-sts::CnnLaunch sts_cnn::launch() const { return CnnLaunch{ctx->stream, ctx->n0, ctx->n1, ctx->n2}; }
+sts::CnnLaunch sts_cnn::launch() const {
+  return CnnLaunch{ctx->stream, ctx->n0, ctx->n1, ctx->n2,
+                   (ctx->debug & STS_DEBUG_WG_REVERSE) ? 1 : 0};
+}
 
 namespace {
 

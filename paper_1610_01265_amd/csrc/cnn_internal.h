@@ -18,6 +18,7 @@ constexpr int kCnnFrag = 14 * 64 * 8;            // bf16 MFMA A fragments per la
 struct CnnLaunch {
   hipStream_t stream;
   int n0, n1, n2;
+  int rev;  // debug: reversed workgroup order of the plane-marching kernels
 };
 
 // kind: 0 ReLU -> bf16 [cells][16]; 1 channel 0 -> FP32 [cells];

@@ -69,12 +69,13 @@ template <int MODE>
 __global__ void __launch_bounds__(256)
     k_conv(CnnGrid g, const __bf16 *__restrict__ in, const __bf16 *__restrict__ wfrag,
            const float *__restrict__ bias, const __bf16 *__restrict__ mask,
-           __bf16 *__restrict__ out_bf, float *__restrict__ outf, int CI, int nchunk) {
+           __bf16 *__restrict__ out_bf, float *__restrict__ outf, int CI, int nchunk, int rev) {
   constexpr int PP = CNN_PPI, RS = CNN_PPI + 2;  // planes per iteration, ring slots
   __shared__ __attribute__((aligned(16))) __bf16 s_in[RS][PLC * CC];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int ntk = (g.n2 + TKC - 1) / TKC, ntj = (g.n1 + TJC - 1) / TJC;
-  const int bx = blockIdx.x % ntk, by = (blockIdx.x / ntk) % ntj, bz = blockIdx.x / (ntk * ntj);
+  const int w = wg_index(rev);
+  const int bx = w % ntk, by = (w / ntk) % ntj, bz = w / (ntk * ntj);
   const int k0 = bx * TKC, j0 = by * TJC;
   const int i0 = bz * CI, i1 = min(i0 + CI, g.n0);
   (void)nchunk;
@@ -228,7 +229,7 @@ constexpr int TCP = TJC * TKC + TJC * TKC / 8;   // padded cells of the dout til
 
 __global__ void __launch_bounds__(256, 2)
     k_wgrad(CnnGrid g, const __bf16 *__restrict__ act, const __bf16 *__restrict__ dout,
-            float *__restrict__ part, int CI, int nitems) {
+            float *__restrict__ part, int CI, int nitems, int rev) {
   __shared__ __attribute__((aligned(16))) __bf16 s_in[2][PLCP * CC];
   __shared__ __attribute__((aligned(16))) __bf16 s_d[2][TCP * CC];
   const int t = threadIdx.x, lane = t & 63;
@@ -252,7 +253,8 @@ __global__ void __launch_bounds__(256, 2)
   constexpr int NCH = PLC * 2;
   constexpr int NLD = (NCH + 255) / 256;
 
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+  const int w = wg_index(rev);
+  for (int item = w; item < nitems; item += gridDim.x) {
     const int bx = item % ntk, by = (item / ntk) % ntj, bz = item / (ntk * ntj);
     const int k0 = bx * TKC, j0 = by * TJC;
     const int i0 = bz * CI, i1 = min(i0 + CI, g.n0);
@@ -377,7 +379,7 @@ __global__ void __launch_bounds__(256, 2)
     for (int e = 0; e < 4; ++e) red[wv * 256 + (4 * grp + e) * 16 + cl] = acc[q][e];
     __syncthreads();
     const float s4 = red[t] + red[256 + t] + red[512 + t] + red[768 + t];
-    part[((size_t)blockIdx.x * (NTAP + 1) + q) * 256 + t] = s4;
+    part[((size_t)w * (NTAP + 1) + q) * 256 + t] = s4;
     __syncthreads();
   }
 }
@@ -537,19 +539,19 @@ void launch_cnn_conv(const CnnLaunch &L, int mode, const void *in, const void *w
   __bf16 *pob = (__bf16 *)out_bf;
   switch (mode) {
     case CV_RELU:
-      hipLaunchKernelGGL(k_conv<CV_RELU>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      hipLaunchKernelGGL(k_conv<CV_RELU>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk, L.rev);
       break;
     case CV_LAST:
-      hipLaunchKernelGGL(k_conv<CV_LAST>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      hipLaunchKernelGGL(k_conv<CV_LAST>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk, L.rev);
       break;
     case CV_MASK:
-      hipLaunchKernelGGL(k_conv<CV_MASK>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      hipLaunchKernelGGL(k_conv<CV_MASK>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk, L.rev);
       break;
     case CV_OUT4:
-      hipLaunchKernelGGL(k_conv<CV_OUT4>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      hipLaunchKernelGGL(k_conv<CV_OUT4>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk, L.rev);
       break;
     default:
-      hipLaunchKernelGGL(k_conv<CV_F32>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk);
+      hipLaunchKernelGGL(k_conv<CV_F32>, grid, blk, 0, L.stream, g, pin, pw, bias, pm, pob, outf, CI, nchunk, L.rev);
   }
 }
 
@@ -563,7 +565,7 @@ void launch_cnn_wgrad(const CnnLaunch &L, const void *act, const void *dout, flo
   const int nitems = ntk * ntj * ((L.n0 + CI - 1) / CI);
   const int nwg = std::min(nitems, cnn_wgrad_parts());
   hipLaunchKernelGGL(k_wgrad, dim3(nwg), dim3(256), 0, L.stream, gr, (const __bf16 *)act,
-                     (const __bf16 *)dout, part, CI, nitems);
+                     (const __bf16 *)dout, part, CI, nitems, L.rev);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3((NTAP + 1) * 256 / WR_OUT), dim3(WR_OUT * WR_SLICES), 0,
                      L.stream, part, nwg, g);
 }

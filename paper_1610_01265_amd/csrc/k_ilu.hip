@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(FTH)
     k_ilu_factor(Grid g, Coef C, double dt, BlockGeo bg, double *__restrict__ fac, int *bad) {
   __shared__ double sL[9][MAXB];
   __shared__ double sD[MAXB];
-  const int bid = xcd_order(blockIdx.x, gridDim.x), t = threadIdx.x;
+  const int bid = xcd_order(wg_index(g.wg_rev), gridDim.x), t = threadIdx.x;
   int o0, o1, o2, e0, e1, e2;
   bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
   const int B1 = bg.B1, B2 = bg.B2, BS = bg.B0 * B1 * B2;
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(ATH)
   __shared__ double sI[MAXB];  // 1 / D
   __shared__ double sz[MAXB];
   __shared__ double sr[MAXB];
-  const int bid = xcd_order(blockIdx.x, gridDim.x), t = threadIdx.x;
+  const int bid = xcd_order(wg_index(g.wg_rev), gridDim.x), t = threadIdx.x;
   int o0, o1, o2, e0, e1, e2;
   bg.origin(g, bid, o0, o1, o2, e0, e1, e2);
   const int B1 = bg.B1, B2 = bg.B2, BS = bg.B0 * B1 * B2;
@@ -381,7 +381,8 @@ __global__ void __launch_bounds__(ATH)
   };
   double rz = 0.0, rr = 0.0;
   Blk8 B;
-  int bid = blockIdx.x;
+  const int w = wg_index(g.wg_rev);
+  int bid = w;
   if (bid < nblk) fetch(bid, B);
   for (; bid < nblk; bid += gridDim.x) {
     // stage this block: factors -> LDS; x, r updates; r -> LDS (0 outside the grid)
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(ATH)
     }
     __syncthreads();  // the LDS is restaged for the next block
   }
-  if (part) wg_sum2<ATH>(rz, rr, t, part + blockIdx.x, part + cap + blockIdx.x);
+  if (part) wg_sum2<ATH>(rz, rr, t, part + w, part + cap + w);
 }
 
 BlockGeo block_geo(const sts_ctx *c, const int block[3]) {

@@ -36,7 +36,12 @@ struct RDims {
   long long ne[3], nf[3];  // edges / faces per component
   const double *tab;       // 18 one-dimensional weight tables
   int off[18];
+  int rev;                 // debug: reversed workgroup order
 };
+
+// the workgroup's logical 3D index (reversed along each axis in the
+// reversed-order self-check; the work and partial slot go with it)
+__device__ __forceinline__ int rblk(int b, int n, int rev) { return rev ? n - 1 - b : b; }
 
 enum { R_H = 0, T_H = 3, P_H = 6, R_W = 9, T_W = 12, P_W = 15 };  // + axis
 
@@ -84,9 +89,10 @@ __global__ void __launch_bounds__(RT) k_rcurl(RDims d, const double *__restrict_
                                               double *__restrict__ Phi) {
   // threads: phi index across lanes, theta across threads / blocks; the
   // workgroup strides over the r-planes of the three face arrays
-  const int k = blockIdx.x * RX + threadIdx.x, j = blockIdx.y * RY + threadIdx.y;
+  const int k = rblk(blockIdx.x, gridDim.x, d.rev) * RX + threadIdx.x,
+            j = rblk(blockIdx.y, gridDim.y, d.rev) * RY + threadIdx.y;
   const int zt = d.m0 + 2 * d.n0;
-  for (int z = blockIdx.z; z < zt; z += gridDim.z) {
+  for (int z = rblk(blockIdx.z, gridDim.z, d.rev); z < zt; z += gridDim.z) {
     double phi, w;
     long long q;
     if (z < d.m0) {  // r-face (i < m0, j < n1, k < n2)
@@ -158,9 +164,10 @@ __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict
                                                const double *__restrict__ Wf, RArgs a) {
   const double *Fr = Phi, *Ft = Phi + d.nf[0], *Fp = Phi + d.nf[0] + d.nf[1];
   double acc1 = 0.0, acc2 = 0.0;
-  const int k = blockIdx.x * RX + threadIdx.x, j = blockIdx.y * RY + threadIdx.y;
+  const int k = rblk(blockIdx.x, gridDim.x, d.rev) * RX + threadIdx.x,
+            j = rblk(blockIdx.y, gridDim.y, d.rev) * RY + threadIdx.y;
   const int zt = d.n0 + 2 * d.m0;
-  for (int z = blockIdx.z; z < zt; z += gridDim.z) {
+  for (int z = rblk(blockIdx.z, gridDim.z, d.rev); z < zt; z += gridDim.z) {
     bool fixed;
     double s = 0.0, h, wsum = 0.0;
     long long e;
@@ -244,7 +251,9 @@ __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict
     }
   }
   const int tid = threadIdx.y * RX + threadIdx.x;
-  const int wg = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int wg = (rblk(blockIdx.z, gridDim.z, d.rev) * gridDim.y +
+                  rblk(blockIdx.y, gridDim.y, d.rev)) * gridDim.x +
+                 rblk(blockIdx.x, gridDim.x, d.rev);
   if (MODE == RC_GERSH) {
     __shared__ double red[RT];
     red[tid] = acc1;
@@ -327,6 +336,7 @@ static RDims rdims(const sts_ctx *c) {
   }
   d.tab = c->d_rtab;
   for (int t = 0; t < 18; ++t) d.off[t] = c->res_off[t];
+  d.rev = (c->debug & STS_DEBUG_WG_REVERSE) ? 1 : 0;
   return d;
 }
 

@@ -38,10 +38,12 @@ def _run_all(sts, w, ctx):
     u = T.clone()
     out["s"] = ctx.rkl2_step(u, dt)
     out["rkl2"] = _host(u)
-    for name, pc in (("jacobi", sts.PC_JACOBI), ("ilu0", sts.PC_BLOCK_ILU0),
-                     ("factor", sts.PC_FACTOR)):
+    for name, pc, blk in (("jacobi", sts.PC_JACOBI, (8, 8, 8)),
+                          ("ilu0", sts.PC_BLOCK_ILU0, (8, 8, 8)),
+                          ("ilu0_ragged", sts.PC_BLOCK_ILU0, (4, 5, 6)),
+                          ("factor", sts.PC_FACTOR, (8, 8, 8))):
         x = T.clone()
-        it, rel, st = ctx.be_pcg_solve(T, x, dt, pc=pc, block=(8, 8, 8), rtol=1e-10)
+        it, rel, st = ctx.be_pcg_solve(T, x, dt, pc=pc, block=blk, rtol=1e-10)
         out[name] = (it, rel, _host(x))
     b = [_cuda(w[k]) for k in ("br", "bt", "bp")]
     u = T.clone()
@@ -71,9 +73,57 @@ def test_reversed_workgroup_order_is_bitwise_identical(gpu_lib, shape):
     for key in ("F", "rkl2", "nl"):
         assert np.array_equal(a[key], b[key]), key
     assert a["s"] == b["s"] and a["s_nl"] == b["s_nl"]
-    for key in ("jacobi", "ilu0", "factor"):
+    for key in ("jacobi", "ilu0", "ilu0_ragged", "factor"):
         assert a[key][0] == b[key][0] and a[key][1] == b[key][1], key
         assert np.array_equal(a[key][2], b[key][2]), key
+
+
+def test_reversed_order_cnn_and_resistivity(gpu_lib):
+    """The same self-check for the CNN kernels (convolution, input and weight
+    gradients, a training step) and the resistivity operator and its solve."""
+    import torch
+    sts = gpu_lib
+    shape = (20, 12, 130)
+    w = small_shell(shape, seed=6)
+    rng = np.random.default_rng(7)
+    n = int(np.prod(shape))
+    x16 = torch.from_numpy(rng.standard_normal((n, 16)).astype(np.float32)).cuda().to(torch.bfloat16)
+    d16 = torch.from_numpy(rng.standard_normal((n, 16)).astype(np.float32)).cuda().to(torch.bfloat16)
+    wts = (0.05 * rng.standard_normal(15169)).astype(np.float32)
+    res = []
+    for flags in (0, sts.DEBUG_WG_REVERSE):
+        ctx = gpu_spitzer(sts, w["rf"], w["thf"], w["phf"], w["T"], w["br"], w["bt"], w["bp"],
+                          w["kappa0"], BC, u_lo=w["T_inner"])
+        ctx.set_debug(flags)
+        net = sts.Cnn(ctx)
+        net.set_weights(wts)
+        out = {"conv": _host(net.conv(1, sts.CNN_RELU, x16).float()),
+               "igrad": _host(net.conv(2, sts.CNN_INPUT_GRAD, d16, mask=x16).float()),
+               "wgrad": _host(net.weight_grad(1, x16, d16))}
+        T = _cuda(w["T"])
+        dt = 30.0 * ctx.dt_euler()
+        F0 = ctx.apply_F(T)
+        net.set_norm(1.0 / float(torch.max(torch.abs(F0))), float(T.mean()), 1e-6, 1e-3)
+        out["loss"] = net.train_step(F0, dt, T, T + 1.0, 1e-3)
+        out["weights"] = net.get_weights()
+        net.close()
+        ctx.set_resistivity(0.3)
+        ne = sum(ctx.resistivity_sizes())
+        E = torch.from_numpy(rng.standard_normal(ne)).cuda() if flags == 0 else E0
+        E0 = E
+        out["rF"] = _host(ctx.apply_F_resistivity(E))
+        xE = E.clone()
+        it, rel, _ = ctx.resistivity_be_pcg_solve(E, xE, 50.0 * ctx.resistivity_dt_euler(),
+                                                  rtol=1e-10)
+        out["rsolve"] = (it, rel, _host(xE))
+        res.append(out)
+        ctx.close()
+    a, b = res
+    for key in ("conv", "igrad", "wgrad", "weights", "rF"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["loss"] == b["loss"]
+    assert a["rsolve"][:2] == b["rsolve"][:2]
+    assert np.array_equal(a["rsolve"][2], b["rsolve"][2])
 
 
 def test_profile_counts_launches(gpu_lib):

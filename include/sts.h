@@ -234,11 +234,14 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
  * grid (no wrap across a periodic axis); with a positive diagonal G is
  * nonsingular and M^-1 symmetric positive definite.  Layout: device FP32
  * g[4][n0][n1][n2], g[0] = G[c, c], g[1 + a] = G[c, c - e_a] (entries whose
- * neighbour does not exist are ignored).  */
+ * neighbour does not exist are ignored).  The context stores the entries
+ * rounded to BF16 (to nearest, ties to even): every application, solve and
+ * objective uses the rounded factor; vectors and sums stay FP64.  */
 
-/* sts_set_pc_factor - copies g into the context (used by be_pcg_solve with
- * STS_PC_FACTOR until the next call).  STS_EINVAL if a diagonal entry is not
- * finite and positive or another entry is not finite.  Synchronises.  */
+/* sts_set_pc_factor - stores g, rounded to BF16, in the context (used by
+ * be_pcg_solve with STS_PC_FACTOR until the next call).  STS_EINVAL if a
+ * rounded diagonal entry is not finite and positive or another entry is not
+ * finite.  Synchronises.  */
 sts_status sts_set_pc_factor(sts_ctx *ctx, const float *g);
 /* sts_apply_pc_factor - z = G (G^T r) with the context's factor; r, z device
  * FP64 [n0][n1][n2], not overlapping.  */

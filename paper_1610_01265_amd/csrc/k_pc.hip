@@ -1,9 +1,11 @@
 // The factored preconditioner M^-1 = G G^T of the backward-Euler PCG, with G
 // lower triangular in the cells' lexicographic order (r slowest, phi
 // fastest): row c holds the cell and its -1 neighbours c - e_a that lie in
-// the grid without wrapping across the periodic phi seam.  Entries are FP32
-// arrays g[q][cell]: g[0] = G[c, c], g[1 + a] = G[c, c - e_a] (ignored where
-// that neighbour does not exist); vectors and arithmetic are FP64.
+// the grid without wrapping across the periodic phi seam.  Entries are BF16
+// arrays g[q][cell] (a preconditioner's entries need no more: any G with a
+// positive diagonal gives an SPD M^-1, and the PCG iterates stay FP64):
+// g[0] = G[c, c], g[1 + a] = G[c, c - e_a] (ignored where that neighbour does
+// not exist); vectors and arithmetic are FP64.
 //
 //   (G^T x)_c = g0_c x_c + sum_a g_(1+a)(c + e_a) x_(c + e_a)
 //   (G x)_c   = g0_c x_c + sum_a g_(1+a)(c) x_(c - e_a)
@@ -65,30 +67,30 @@ __device__ __forceinline__ void for_cells(const PcDims &d, F &&f) {
 
 // t = G^T x (- sub)
 __global__ void __launch_bounds__(NT)
-    k_pc_gt(PcDims d, const float *__restrict__ g, const double *__restrict__ x,
+    k_pc_gt(PcDims d, const __bf16 *__restrict__ g, const double *__restrict__ x,
             const double *__restrict__ sub, double *__restrict__ t, const PcgScalars *sc) {
   if (sc && sc->done) return;
-  const float *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
+  const __bf16 *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
   for_cells(d, [&](int i, int j, int k, long long c) {
-    double v = (double)g[c] * x[c];
-    if (i + 1 < d.n0) v += (double)g1[c + d.n12] * x[c + d.n12];
-    if (j + 1 < d.n1) v += (double)g2[c + d.n2] * x[c + d.n2];
-    if (k + 1 < d.n2) v += (double)g3[c + 1] * x[c + 1];
+    double v = (double)(float)g[c] * x[c];
+    if (i + 1 < d.n0) v += (double)(float)g1[c + d.n12] * x[c + d.n12];
+    if (j + 1 < d.n1) v += (double)(float)g2[c + d.n2] * x[c + d.n2];
+    if (k + 1 < d.n2) v += (double)(float)g3[c + 1] * x[c + 1];
     t[c] = sub ? v - sub[c] : v;
   });
 }
 
 // z = G t
 __global__ void __launch_bounds__(NT)
-    k_pc_g(PcDims d, const float *__restrict__ g, const double *__restrict__ t,
+    k_pc_g(PcDims d, const __bf16 *__restrict__ g, const double *__restrict__ t,
            double *__restrict__ z, const PcgScalars *sc) {
   if (sc && sc->done) return;
-  const float *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
+  const __bf16 *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
   for_cells(d, [&](int i, int j, int k, long long c) {
-    double v = (double)g[c] * t[c];
-    if (i > 0) v += (double)g1[c] * t[c - d.n12];
-    if (j > 0) v += (double)g2[c] * t[c - d.n2];
-    if (k > 0) v += (double)g3[c] * t[c - 1];
+    double v = (double)(float)g[c] * t[c];
+    if (i > 0) v += (double)(float)g1[c] * t[c - d.n12];
+    if (j > 0) v += (double)(float)g2[c] * t[c - d.n2];
+    if (k > 0) v += (double)(float)g3[c] * t[c - 1];
     z[c] = v;
   });
 }
@@ -103,7 +105,7 @@ __device__ __forceinline__ double inv_sqrt_diag(const Grid &gr, const double *sd
 // A non-finite entry sets *bad.
 __global__ void __launch_bounds__(NT)
     k_pc_build(PcDims d, Grid gr, const double *__restrict__ sdiag, double dt,
-               const float *__restrict__ o4, float *__restrict__ g, int *bad) {
+               const float *__restrict__ o4, __bf16 *__restrict__ g, int *bad) {
   for_cells(d, [&](int i, int j, int k, long long c) {
     const double dd = inv_sqrt_diag(gr, sdiag, dt, i, j, k, c);
     double o[4] = {0.0, 0.0, 0.0, 0.0};
@@ -114,11 +116,14 @@ __global__ void __launch_bounds__(NT)
       o[2] = v.z;
       o[3] = v.w;
     }
-    const float e0 = (float)(dd * exp(o[0]));
-    const float e1 = i > 0 ? (float)(dd * o[1]) : 0.0f;
-    const float e2 = j > 0 ? (float)(dd * o[2]) : 0.0f;
-    const float e3 = k > 0 ? (float)(dd * o[3]) : 0.0f;
-    if (!(isfinite(e0) && e0 > 0.0f && isfinite(e1) && isfinite(e2) && isfinite(e3)))
+    // rounded to BF16 through FP32 (ties to even at each step)
+    const __bf16 e0 = (__bf16)(float)(dd * exp(o[0]));
+    const __bf16 e1 = (__bf16)(i > 0 ? (float)(dd * o[1]) : 0.0f);
+    const __bf16 e2 = (__bf16)(j > 0 ? (float)(dd * o[2]) : 0.0f);
+    const __bf16 e3 = (__bf16)(k > 0 ? (float)(dd * o[3]) : 0.0f);
+    const float f0 = (float)e0;
+    if (!(isfinite(f0) && f0 > 0.0f && isfinite((float)e1) && isfinite((float)e2) &&
+          isfinite((float)e3)))
       atomicOr(bad, 1);
     g[c] = e0;
     g[c + d.n] = e1;
@@ -127,14 +132,20 @@ __global__ void __launch_bounds__(NT)
   });
 }
 
-// A caller's factor: the diagonal must be finite and positive, the other
-// entries finite.
+// A caller's FP32 factor rounded to the BF16 store; after rounding the
+// diagonal must be finite and positive, the other entries finite.
 __global__ void __launch_bounds__(NT)
-    k_pc_check(PcDims d, const float *__restrict__ g, int *bad) {
+    k_pc_check(PcDims d, const float *__restrict__ g32, __bf16 *__restrict__ g, int *bad) {
   for_cells(d, [&](int i, int j, int k, long long c) {
-    const float e0 = g[c], e1 = g[c + d.n], e2 = g[c + 2 * d.n], e3 = g[c + 3 * d.n];
-    if (!(isfinite(e0) && e0 > 0.0f && isfinite(e1) && isfinite(e2) && isfinite(e3)))
-      atomicOr(bad, 1);
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const __bf16 e = (__bf16)g32[c + q * d.n];
+      const float f = (float)e;
+      ok = ok && isfinite(f) && (q > 0 || f > 0.0f);
+      g[c + q * d.n] = e;
+    }
+    if (!ok) atomicOr(bad, 1);
   });
 }
 
@@ -166,7 +177,7 @@ __global__ void __launch_bounds__(NT)
 // (dg0 G_cc, dg_(1+a) d), channels 4..15 zero; partial sums of r.r.
 __global__ void __launch_bounds__(NT)
     k_pc_grad(PcDims d, Grid gr, const double *__restrict__ sdiag, double dt,
-              const float *__restrict__ g, const double *__restrict__ y,
+              const __bf16 *__restrict__ g, const double *__restrict__ y,
               const double *__restrict__ r, const double *__restrict__ s,
               const double *__restrict__ z, double *__restrict__ dg, __bf16 *__restrict__ dout,
               double *part) {
@@ -189,7 +200,7 @@ __global__ void __launch_bounds__(NT)
       __bf16 v[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) v[q] = (__bf16)0.0f;
-      v[0] = (__bf16)(float)(e[0] * (double)g[c]);
+      v[0] = (__bf16)(float)(e[0] * (double)(float)g[c]);
       v[1] = (__bf16)(float)(e[1] * dd);
       v[2] = (__bf16)(float)(e[2] * dd);
       v[3] = (__bf16)(float)(e[3] * dd);
@@ -213,7 +224,7 @@ __global__ void __launch_bounds__(NT)
 // in every workgroup (pcg_alpha), workgroup 0 recording it.
 template <bool FUSE>
 __global__ void __launch_bounds__(NT)
-    k_pc_xr_gt(PcDims d, const float *__restrict__ g, double *__restrict__ x,
+    k_pc_xr_gt(PcDims d, const __bf16 *__restrict__ g, double *__restrict__ x,
                const double *__restrict__ p, const double *__restrict__ rin,
                double *__restrict__ rout, const double *__restrict__ y, double *__restrict__ t,
                double *part, long long cap, PcgScalars *sc, const double *pa, int npa) {
@@ -225,16 +236,16 @@ __global__ void __launch_bounds__(NT)
   } else {
     alpha = sc->alpha;
   }
-  const float *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
+  const __bf16 *g1 = g + d.n, *g2 = g + 2 * d.n, *g3 = g + 3 * d.n;
   double tt = 0.0, rr = 0.0;
   for_cells(d, [&](int i, int j, int k, long long c) {
     const double rn = rin[c] - alpha * y[c];
     x[c] = x[c] + alpha * p[c];
     rout[c] = rn;
-    double v = (double)g[c] * rn;
-    if (i + 1 < d.n0) v += (double)g1[c + d.n12] * (rin[c + d.n12] - alpha * y[c + d.n12]);
-    if (j + 1 < d.n1) v += (double)g2[c + d.n2] * (rin[c + d.n2] - alpha * y[c + d.n2]);
-    if (k + 1 < d.n2) v += (double)g3[c + 1] * (rin[c + 1] - alpha * y[c + 1]);
+    double v = (double)(float)g[c] * rn;
+    if (i + 1 < d.n0) v += (double)(float)g1[c + d.n12] * (rin[c + d.n12] - alpha * y[c + d.n12]);
+    if (j + 1 < d.n1) v += (double)(float)g2[c + d.n2] * (rin[c + d.n2] - alpha * y[c + d.n2]);
+    if (k + 1 < d.n2) v += (double)(float)g3[c + 1] * (rin[c + 1] - alpha * y[c + 1]);
     t[c] = v;
     tt += v * v;
     rr += rn * rn;
@@ -249,32 +260,34 @@ int grid_items(const PcDims &d) { return (int)(d.items < 2048 ? d.items : 2048);
 
 int pc_parts(const sts_ctx *c) { return grid_items(dims_of(c)); }
 
-void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const double *sub,
+void launch_pc_gt(const sts_ctx *c, const void *g, const double *x, const double *sub,
                   double *t, const PcgScalars *sc) {
   STS_PROF(c, "launch_pc_gt");
   const PcDims d = dims_of(c);
-  hipLaunchKernelGGL(k_pc_gt, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, x, sub, t,
-                     sc);
+  hipLaunchKernelGGL(k_pc_gt, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d,
+                     (const __bf16 *)g, x, sub, t, sc);
 }
 
-void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z,
+void launch_pc_g(const sts_ctx *c, const void *g, const double *t, double *z,
                  const PcgScalars *sc) {
   STS_PROF(c, "launch_pc_g");
   const PcDims d = dims_of(c);
-  hipLaunchKernelGGL(k_pc_g, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, t, z, sc);
+  hipLaunchKernelGGL(k_pc_g, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d,
+                     (const __bf16 *)g, t, z, sc);
 }
 
-void launch_pc_build(const sts_ctx *c, double dt, const float *o4, float *g, int *bad) {
+void launch_pc_build(const sts_ctx *c, double dt, const float *o4, void *g, int *bad) {
   STS_PROF(c, "launch_pc_build");
   const PcDims d = dims_of(c);
   hipLaunchKernelGGL(k_pc_build, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
-                     (const double *)c->d_sdiag, dt, o4, g, bad);
+                     (const double *)c->d_sdiag, dt, o4, (__bf16 *)g, bad);
 }
 
-void launch_pc_check(const sts_ctx *c, const float *g, int *bad) {
+void launch_pc_check(const sts_ctx *c, const float *g32, void *g, int *bad) {
   STS_PROF(c, "launch_pc_check");
   const PcDims d = dims_of(c);
-  hipLaunchKernelGGL(k_pc_check, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g, bad);
+  hipLaunchKernelGGL(k_pc_check, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g32,
+                     (__bf16 *)g, bad);
 }
 
 void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T, double tsh,
@@ -285,26 +298,28 @@ void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T,
                      (const double *)c->d_sdiag, dt, lscale, T, tsh, tsc, (__bf16 *)x);
 }
 
-void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y,
+void launch_pc_grad(const sts_ctx *c, double dt, const void *g, const double *y,
                     const double *r, const double *s, const double *z, double *dg, void *dout,
                     double *part) {
   STS_PROF(c, "launch_pc_grad");
   const PcDims d = dims_of(c);
   hipLaunchKernelGGL(k_pc_grad, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, c->grid(),
-                     (const double *)c->d_sdiag, dt, g, y, r, s, z, dg, (__bf16 *)dout, part);
+                     (const double *)c->d_sdiag, dt, (const __bf16 *)g, y, r, s, z, dg,
+                     (__bf16 *)dout, part);
 }
 
-void launch_pc_xr_gt(const sts_ctx *c, const float *g, double *x, const double *p,
+void launch_pc_xr_gt(const sts_ctx *c, const void *g, double *x, const double *p,
                      const double *rin, double *rout, const double *y, double *t, double *part,
                      PcgScalars *sc, const double *pa, int npa) {
   STS_PROF(c, "launch_pc_xr_gt");
   const PcDims d = dims_of(c);
   if (pa)
-    hipLaunchKernelGGL(k_pc_xr_gt<true>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d, g,
-                       x, p, rin, rout, y, t, part, (long long)c->red_cap, sc, pa, npa);
+    hipLaunchKernelGGL(k_pc_xr_gt<true>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d,
+                       (const __bf16 *)g, x, p, rin, rout, y, t, part, (long long)c->red_cap, sc,
+                       pa, npa);
   else
     hipLaunchKernelGGL(k_pc_xr_gt<false>, dim3(grid_items(d)), dim3(TX, TY), 0, c->stream, d,
-                       g, x, p, rin, rout, y, t, part, (long long)c->red_cap, sc,
+                       (const __bf16 *)g, x, p, rin, rout, y, t, part, (long long)c->red_cap, sc,
                        (const double *)nullptr, 0);
 }
 

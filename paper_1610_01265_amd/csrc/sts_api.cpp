@@ -1149,7 +1149,7 @@ sts_status be_pcg_solve(sts_ctx *ctx, const double *u_n, double *x, double dt, i
 // (the sts_* entry points keep the C linkage of their declarations in sts.h)
 
 static sts_status pc_factor_storage(sts_ctx *ctx) {
-  if (!ctx->d_gfac) return dalloc(ctx, (void **)&ctx->d_gfac, (size_t)4 * ctx->ncell * 4);
+  if (!ctx->d_gfac) return dalloc(ctx, (void **)&ctx->d_gfac, (size_t)4 * ctx->ncell * 2);
   return STS_OK;
 }
 
@@ -1159,10 +1159,8 @@ sts_status sts_set_pc_factor(sts_ctx *ctx, const float *g) {
   sts_status st = pc_factor_storage(ctx);
   if (st) return st;
   HIPCHK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
-  launch_pc_check(ctx, g, ctx->d_flag);
+  launch_pc_check(ctx, g, ctx->d_gfac, ctx->d_flag);
   LAUNCHCHK();
-  HIPCHK(hipMemcpyAsync(ctx->d_gfac, g, (size_t)4 * ctx->ncell * 4, hipMemcpyDeviceToDevice,
-                        ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->h_pin, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (*(int *)ctx->h_pin) {
@@ -1224,7 +1222,7 @@ sts_status sts::pc_objective_sweeps(sts_ctx *ctx, double dt, const double *z, do
   double *w = ctx->d_pcobj, *y = w + n, *r = w + 2 * n, *q = w + 3 * n, *s = w + 4 * n,
          *p = w + 5 * n;
   double *part = ctx->d_red;
-  const float *g = ctx->d_gfac;
+  const void *g = ctx->d_gfac;
   launch_pc_g(ctx, g, z, w, nullptr);
   launch_pass_a(ctx, dt, w, nullptr, p, y, part, ctx->d_sc0, 1);
   launch_pc_gt(ctx, g, y, z, r, nullptr);

@@ -129,7 +129,7 @@ struct sts_ctx {
   int red_cap = 0;
   sts::PcgScalars *d_sc = nullptr;
   sts::PcgScalars *h_sc = nullptr;  // pinned mirror
-  float *d_gfac = nullptr;    // factored preconditioner G, FP32 [4][ncell]
+  void *d_gfac = nullptr;     // factored preconditioner G, BF16 [4][ncell]
   bool gfac_set = false;
   double *d_pct = nullptr;    // its PCG work vector t = G^T r
   double *d_pcobj = nullptr;  // sts_pc_objective: w, y, r, q, s, p (6 x ncell)
@@ -297,23 +297,23 @@ int ilu_parts(const sts_ctx *c, const int block[3]);
 // factored preconditioner M^-1 = G G^T (k_pc.hip); g: FP32 [4][ncell]
 int pc_parts(const sts_ctx *c);  // workgroups (partials) of the pc kernels
 // t = G^T x (- sub, may be null); sc (may be null): no-op once sc->done
-void launch_pc_gt(const sts_ctx *c, const float *g, const double *x, const double *sub,
+void launch_pc_gt(const sts_ctx *c, const void *g, const double *x, const double *sub,
                   double *t, const PcgScalars *sc);
 // z = G t; sc (may be null): no-op once sc->done
-void launch_pc_g(const sts_ctx *c, const float *g, const double *t, double *z,
+void launch_pc_g(const sts_ctx *c, const void *g, const double *t, double *z,
                  const PcgScalars *sc);
 // factor from network outputs o4 [cells][4] (null: point Jacobi) at dt
-void launch_pc_build(const sts_ctx *c, double dt, const float *o4, float *g, int *bad);
-void launch_pc_check(const sts_ctx *c, const float *g, int *bad);
+void launch_pc_build(const sts_ctx *c, double dt, const float *o4, void *g, int *bad);
+void launch_pc_check(const sts_ctx *c, const float *g32, void *g, int *bad);
 void launch_pc_pack(const sts_ctx *c, double dt, double lscale, const double *T, double tsh,
                     double tsc, void *x);
-void launch_pc_grad(const sts_ctx *c, double dt, const float *g, const double *y,
+void launch_pc_grad(const sts_ctx *c, double dt, const void *g, const double *y,
                     const double *r, const double *s, const double *z, double *dg, void *dout,
                     double *part);
 // x += alpha p, r_out = r_in - alpha y, t = G^T r_out (r_in != r_out); partial
 // sums t.t and r.r to part, part + cap; pa != null: alpha from pass A's
 // partials pa (npa) inside the sweep, else from sc
-void launch_pc_xr_gt(const sts_ctx *c, const float *g, double *x, const double *p,
+void launch_pc_xr_gt(const sts_ctx *c, const void *g, double *x, const double *p,
                      const double *rin, double *rout, const double *y, double *t, double *part,
                      PcgScalars *sc, const double *pa, int npa);
 // host helpers of the factor network (sts_api.cpp): the factor built from

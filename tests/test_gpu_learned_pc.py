@@ -1,13 +1,14 @@
 """GPU parity of the factored preconditioner M^-1 = G G^T and its network
 (STS_PC_FACTOR, cnn_create_pc) against the oracle (oracle/learned_pc.py).
 
-Factors given to both sides are seeded FP32 arrays (the oracle reads the same
-FP32 values in FP64), so the FP64 paths are compared at 1e-12: the
+Factors given to both sides are seeded arrays of BF16-representable values
+(the library stores the entries in BF16; the oracle reads the same values in
+FP64), so the FP64 paths are compared at 1e-12: the
 application z = G G^T r, PCG iterates at equal k (k <= 10), the training
 objective and its gradient in the entries; the converged solve by iteration
 count (within one) and the residual-test bound.  The network's
 factor at known outputs (zero weights, last-layer biases b: o = b) against
-the oracle's entry maps at FP32 rounding; the network gradient against the
+the oracle's entry maps rounded to BF16 as the library rounds them; the network gradient against the
 oracle's FP64 back-propagation with bf16-rounded activations (tolerance as
 the initial-guess network's whole-network test)."""
 import numpy as np
@@ -47,10 +48,10 @@ def _pair(sts, shape, seed=1):
 
 
 def _factor32(op, dt, shape, seed, scale=0.3):
-    """Seeded factor rounded to FP32: the array both sides use."""
+    """Seeded factor rounded to BF16 (stored as FP32): the values both sides use."""
     A19, _ = O.be_system(op, np.zeros(shape), dt)
     o = scale * np.random.default_rng(seed).standard_normal((4,) + tuple(shape))
-    g = LP.factor_entries(o, A19[0]).astype(np.float32)
+    g = RB(LP.factor_entries(o, A19[0])).astype(np.float32)
     return g, g.astype(np.float64)
 
 
@@ -128,6 +129,12 @@ def test_factor_checks(gpu_lib):
     bad[2, 1, 1, 1] = np.nan
     with pytest.raises(sts.StsError):
         ctx.set_pc_factor(_cuda(bad))
+    # a positive FP32 diagonal entry below BF16's smallest value rounds to 0
+    bad = g32.copy()
+    bad[0, 2, 3, 4] = 1e-44
+    with pytest.raises(sts.StsError):
+        ctx.set_pc_factor(_cuda(bad))
+    ctx.set_pc_factor(_cuda(g32))
 
 
 def _pc_net(sts, ctx, params):
@@ -160,17 +167,19 @@ def test_network_factor_at_known_outputs(gpu_lib):
     A19, _ = O.be_system(op, w["T"], dt)
     r = np.random.default_rng(9).standard_normal(shape)
     z = _host(ctx.apply_pc_factor(_cuda(r)))
-    # point Jacobi up to the FP32 storage of d = A_cc^-1/2 (applied twice)
-    assert relmax(z, r / A19[0]) <= 3e-7
+    # point Jacobi up to the BF16 storage of d = A_cc^-1/2 (applied twice)
+    assert relmax(z, r / A19[0]) <= 2 * 2.0 ** -8
+    assert relmax(z, LP.apply_Minv(RB(LP.factor_entries(np.zeros((4,) + shape), A19[0])), r)) \
+        <= 1e-12
     net.close()
     b = [0.25, -0.125, 0.0625, 0.5]
     net = _pc_net(sts, ctx, _zero_params(b))
     net.set_norm(1.2e6, 1e-5)
     assert net.factor(T, dt)
     o = np.stack([np.full(shape, v) for v in b])
-    g = LP.factor_entries(o, A19[0])
+    g = RB(LP.factor_entries(o, A19[0]))  # the library's BF16 entries
     z = _host(ctx.apply_pc_factor(_cuda(r)))
-    assert relmax(z, LP.apply_Minv(g, r)) <= 1e-6  # FP32 entries
+    assert relmax(z, LP.apply_Minv(g, r)) <= 1e-12
     net.close()
 
 
@@ -207,7 +216,7 @@ def test_network_gradient_matches_oracle(gpu_lib):
     # oracle
     x, A19 = _oracle_features(op, w["T"], dt, tsh, tsc)
     y, cache = ocnn.forward(params, x, act_round=RB)
-    g = LP.factor_entries(y, A19[0])
+    g = RB(LP.factor_entries(y, A19[0]))  # the library's BF16 entries
     Lr, dg = LP.loss_and_grad(g, lambda v: O.apply19(A19, v), z)
     do = LP.grad_outputs(dg, g, A19[0])
     grads = ocnn.backward(params, cache, do)

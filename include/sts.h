@@ -346,6 +346,20 @@ long long cnn_num_params(const sts_cnn *net);
 sts_status cnn_set_weights(sts_cnn *net, const float *w, long long n);
 sts_status cnn_get_weights(sts_cnn *net, float *w, long long n);
 
+/* cnn_state_size / cnn_get_state / cnn_set_state - the whole training state,
+ * for checkpoint and resume (not in the paper): buf (HOST, FP32,
+ * cnn_state_size = 3 x layers x 6928 values) holds the padded master
+ * parameters, then Adam's first and second moments, each in the padded
+ * layout cnn_weight_grad writes; meta (HOST, 8 values) = Adam step count,
+ * the four scalings of cnn_set_norm (the factor network uses T_shift and
+ * T_scale), beta1, beta2, eps.  Setting checks finiteness, second moments
+ * >= 0, zeros at the padding entries and the ranges of cnn_set_norm and
+ * cnn_set_adam (STS_EINVAL otherwise); a network set from a state continues
+ * training exactly as the one the state was taken from.  Synchronise.  */
+long long cnn_state_size(const sts_cnn *net);
+sts_status cnn_get_state(sts_cnn *net, float *buf, long long n, double meta[8]);
+sts_status cnn_set_state(sts_cnn *net, const float *buf, long long n, const double meta[8]);
+
 /* cnn_set_norm - the four input / output scalings above (finite; the
  * scales nonzero).  Defaults 1, 0, 1, 1.  */
 sts_status cnn_set_norm(sts_cnn *net, double rhs_scale, double T_shift, double T_scale,

@@ -73,6 +73,9 @@ def load():
         "cnn_num_params": (ctypes.c_longlong, [P]),
         "cnn_set_weights": (I, [P, P, ctypes.c_longlong]),
         "cnn_get_weights": (I, [P, P, ctypes.c_longlong]),
+        "cnn_state_size": (ctypes.c_longlong, [P]),
+        "cnn_get_state": (I, [P, P, ctypes.c_longlong, P]),
+        "cnn_set_state": (I, [P, P, ctypes.c_longlong, P]),
         "cnn_set_norm": (I, [P, D, D, D, D]),
         "cnn_moments": (I, [P, P, P, D, PD]),
         "cnn_pack_input": (I, [P, P, D, P, P]),
@@ -111,7 +114,7 @@ def exported_symbols():
             "sts_resistivity_sizes", "apply_F_resistivity", "resistivity_dt_euler",
             "resistivity_be_pcg_solve", "be_pcg_solve",
             "sts_be_residual", "cnn_create", "cnn_destroy", "cnn_num_params", "cnn_set_weights",
-            "cnn_get_weights", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
+            "cnn_get_weights", "cnn_state_size", "cnn_get_state", "cnn_set_state", "cnn_set_norm", "cnn_moments", "cnn_pack_input", "cnn_conv",
             "cnn_weight_grad", "cnn_forward", "cnn_train_step", "cnn_set_adam", "cnn_adam_step",
             "cnn_guess", "sts_set_pc_factor", "sts_apply_pc_factor", "sts_pc_objective",
             "cnn_create_pc", "cnn_pc_set_norm", "cnn_pc_factor", "cnn_pc_train_step",
@@ -434,6 +437,28 @@ class Cnn:
         a = np.empty(self.nparam, np.float32)
         self._chk(self._lib.cnn_get_weights(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size))
         return a
+
+    def get_state(self):
+        """The training state: {"buf": FP32 [3 x layers x 6928] (master parameters, Adam
+        moments), "meta": FP64 [8] (step, four scalings, beta1, beta2, eps)}."""
+        import numpy as np
+        self.ctx._sync_stream()
+        n = self._lib.cnn_state_size(self._h)
+        buf = np.empty(n, np.float32)
+        meta = np.empty(8, np.float64)
+        self._chk(self._lib.cnn_get_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), n,
+                                          meta.ctypes.data_as(ctypes.c_void_p)))
+        return {"buf": buf, "meta": meta}
+
+    def set_state(self, state):
+        import numpy as np
+        self.ctx._sync_stream()
+        buf = np.ascontiguousarray(state["buf"], dtype=np.float32)
+        meta = np.ascontiguousarray(state["meta"], dtype=np.float64)
+        if meta.size != 8:
+            raise ValueError("meta must hold 8 values")
+        self._chk(self._lib.cnn_set_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size,
+                                          meta.ctypes.data_as(ctypes.c_void_p)))
 
     def set_norm(self, rhs_scale, T_shift, T_scale, delta_scale):
         self._chk(self._lib.cnn_set_norm(self._h, float(rhs_scale), float(T_shift),

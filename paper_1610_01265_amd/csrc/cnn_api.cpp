@@ -269,6 +269,66 @@ sts_status cnn_get_weights(sts_cnn *net, float *w, long long n) {
   return STS_OK;
 }
 
+long long cnn_state_size(const sts_cnn *net) {
+  return net ? 3LL * net->layers * kCnnPPerLayer : 0;
+}
+
+sts_status cnn_get_state(sts_cnn *net, float *buf, long long n, double meta[8]) {
+  if (!net) return STS_EINVAL;
+  const long long np = (long long)net->layers * kCnnPPerLayer;
+  if (!buf || !meta || n != 3 * np) NFAIL(STS_EINVAL, "cnn_get_state: need cnn_state_size values");
+  hipStream_t s = net->ctx->stream;
+  NHIPCHK(hipMemcpyAsync(buf, net->d_P, np * 4, hipMemcpyDeviceToHost, s));
+  NHIPCHK(hipMemcpyAsync(buf + np, net->d_M, np * 4, hipMemcpyDeviceToHost, s));
+  NHIPCHK(hipMemcpyAsync(buf + 2 * np, net->d_V, np * 4, hipMemcpyDeviceToHost, s));
+  NHIPCHK(hipStreamSynchronize(s));
+  const double m[8] = {(double)net->step, net->rhs_scale, net->t_shift, net->t_scale,
+                       net->delta_scale, net->adam_b1, net->adam_b2, net->adam_eps};
+  for (int q = 0; q < 8; ++q) meta[q] = m[q];
+  return STS_OK;
+}
+
+sts_status cnn_set_state(sts_cnn *net, const float *buf, long long n, const double meta[8]) {
+  if (!net) return STS_EINVAL;
+  const long long np = (long long)net->layers * kCnnPPerLayer;
+  if (!buf || !meta || n != 3 * np) NFAIL(STS_EINVAL, "cnn_set_state: need cnn_state_size values");
+  for (long long q = 0; q < n; ++q)
+    if (!std::isfinite(buf[q])) NFAIL(STS_EINVAL, "cnn_set_state: non-finite value");
+  for (long long q = 2 * np; q < n; ++q)
+    if (buf[q] < 0.0f) NFAIL(STS_EINVAL, "cnn_set_state: negative second moment");
+  if (!(meta[0] >= 0.0 && meta[0] < 2147483647.0 && meta[0] == (double)(long long)meta[0]))
+    NFAIL(STS_EINVAL, "cnn_set_state: bad step count");
+  if (!finite_nonzero(meta[1]) || !std::isfinite(meta[2]) || !finite_nonzero(meta[3]) ||
+      !finite_nonzero(meta[4]))
+    NFAIL(STS_EINVAL, "cnn_set_state: scalings must be finite and nonzero");
+  if (!(meta[5] >= 0.0 && meta[5] < 1.0) || !(meta[6] >= 0.0 && meta[6] < 1.0) ||
+      !(meta[7] > 0.0) || !std::isfinite(meta[7]))
+    NFAIL(STS_EINVAL, "cnn_set_state: bad Adam constants");
+  // the padding entries, which hold no parameter, stay zero
+  std::vector<float> mask(np);
+  hipStream_t s = net->ctx->stream;
+  NHIPCHK(hipMemcpyAsync(mask.data(), net->d_mask, np * 4, hipMemcpyDeviceToHost, s));
+  NHIPCHK(hipStreamSynchronize(s));
+  for (long long q = 0; q < np; ++q)
+    if (mask[q] == 0.0f && (buf[q] != 0.0f || buf[np + q] != 0.0f || buf[2 * np + q] != 0.0f))
+      NFAIL(STS_EINVAL, "cnn_set_state: nonzero value at a padding entry");
+  NHIPCHK(hipMemcpyAsync(net->d_P, buf, np * 4, hipMemcpyHostToDevice, s));
+  NHIPCHK(hipMemcpyAsync(net->d_M, buf + np, np * 4, hipMemcpyHostToDevice, s));
+  NHIPCHK(hipMemcpyAsync(net->d_V, buf + 2 * np, np * 4, hipMemcpyHostToDevice, s));
+  refresh_frags(net);
+  NLAUNCHCHK();
+  NHIPCHK(hipStreamSynchronize(s));
+  net->step = (int)meta[0];
+  net->rhs_scale = meta[1];
+  net->t_shift = meta[2];
+  net->t_scale = meta[3];
+  net->delta_scale = meta[4];
+  net->adam_b1 = (float)meta[5];
+  net->adam_b2 = (float)meta[6];
+  net->adam_eps = (float)meta[7];
+  return STS_OK;
+}
+
 sts_status cnn_set_norm(sts_cnn *net, double rhs_scale, double T_shift, double T_scale,
                         double delta_scale) {
   if (!net) return STS_EINVAL;

@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   // tile through the scalar unit), the (j - 1) neighbours through LDS from
   // the wavefront of the row above (the first row loads them).  This needs
   // the own values first and a barrier; measured -8 % per RKL2 stage at
-  // 256 x 256 x 512, but +2 % per PCG pass A (non-temporal coefficient
+  // 256 x 256 x 512, but +3.5 % per PCG pass A (non-temporal coefficient
   // streams), which keeps the cached neighbour loads.
   constexpr bool xlane = OP == OP_SPITZER && MODE != M_PA;
   auto load_nbr = [&](int ip, Loads &L) {

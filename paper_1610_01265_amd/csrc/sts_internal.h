@@ -294,7 +294,7 @@ void launch_pass_b_ilu(const sts_ctx *c, const int block[3], const double *fac, 
                        const PcgScalars *sc);
 int ilu_parts(const sts_ctx *c, const int block[3]);
 
-// factored preconditioner M^-1 = G G^T (k_pc.hip); g: FP32 [4][ncell]
+// factored preconditioner M^-1 = G G^T (k_pc.hip); g: BF16 [4][ncell]
 int pc_parts(const sts_ctx *c);  // workgroups (partials) of the pc kernels
 // t = G^T x (- sub, may be null); sc (may be null): no-op once sc->done
 void launch_pc_gt(const sts_ctx *c, const void *g, const double *x, const double *sub,

@@ -353,7 +353,8 @@ class Context:
         self._check(self._lib.sts_set_debug(self._h, int(flags)))
 
     def set_pc_factor(self, g):
-        """The STS_PC_FACTOR factor from a device FP32 tensor [4, n0, n1, n2]."""
+        """The STS_PC_FACTOR factor from a device FP32 tensor [4, n0, n1, n2] (stored rounded
+        to BF16)."""
         self._sync_stream()
         self._check(self._lib.sts_set_pc_factor(self._h, _ptr(g, self.ncell, "g", 4,
                                                               dtype=torch.float32)))

@@ -6,7 +6,8 @@ tests pin that bookkeeping:
   * maxit = 0 returns the initial guess untouched with STS_NOT_CONVERGED;
   * a solve allowed exactly the iteration count at which it converges reports
     convergence with that count and the same x, bit for bit, as an unlimited
-    solve; one iteration fewer reports STS_NOT_CONVERGED after that many;
+    solve; one iteration fewer reports STS_NOT_CONVERGED after that many
+    (Jacobi, block ILU0 and the factored preconditioner);
   * the same for the FP32 form (total inner iterations)."""
 import numpy as np
 import pytest
@@ -62,10 +63,17 @@ def _solve(c, w, dt, pc, maxit):
     return it, rel, st, _host(x)
 
 
-@pytest.mark.parametrize("pc", [0, 1])
+@pytest.mark.parametrize("pc", [0, 1, 2])
 def test_fp64_stop_at_maxit(gpu_lib, w, pc):
+    """Jacobi, block ILU0 and the factored M^-1 = G G^T (a seeded factor)."""
     c = _ctx(gpu_lib, w)
     dt = _dt(w)
+    if pc == gpu_lib.PC_FACTOR:
+        rng = np.random.default_rng(12)
+        g = np.zeros((4,) + w["T"].shape, np.float32)
+        g[0] = 1e-3 * (1.0 + 0.1 * rng.random(w["T"].shape))
+        g[1:] = 1e-4 * rng.standard_normal((3,) + w["T"].shape)
+        c.set_pc_factor(_cuda(g))
     n, rel, st, x = _solve(c, w, dt, pc, 10000)
     assert st == 0 and n > 2 and rel <= 1e-9
     it0, _, st0, x0 = _solve(c, w, dt, pc, 0)

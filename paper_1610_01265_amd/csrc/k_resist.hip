@@ -81,67 +81,72 @@ __device__ __forceinline__ double ev(const double *E, long long idx, bool fixed)
   return E[idx];
 }
 
+// the contiguous run [i0, i1) of r-planes of z-block b out of nb over n planes
+__device__ __forceinline__ void plane_run(int n, int b, int nb, int &i0, int &i1) {
+  const int per = (n + nb - 1) / nb;
+  i0 = min(n, b * per);
+  i1 = min(n, i0 + per);
+}
+
 // Per face (component order r, t, p): KIND 0: Phi~ = w C E; KIND 1: w times
 // the number of the face's interior edges (Gershgorin rows); KIND 2: w.
 enum { RK_FLUX = 0, RK_COUNT = 1, RK_WEIGHT = 2 };
+
+template <int KIND>
+__device__ __forceinline__ double face_val(bool f1, bool f2, bool f3, bool f4, double flux) {
+  if (KIND == RK_WEIGHT) return 1.0;
+  if (KIND == RK_COUNT) return (!f1) + (!f2) + (!f3) + (!f4);
+  return flux;
+}
+
 template <int MASK, int KIND>
 __global__ void __launch_bounds__(RT) k_rcurl(RDims d, const double *__restrict__ E,
                                               double *__restrict__ Phi) {
-  // threads: phi index across lanes, theta across threads / blocks; the
-  // workgroup strides over the r-planes of the three face arrays
+  // threads: phi index across lanes, theta across threads / blocks; each
+  // workgroup takes a contiguous run of r-planes and forms the three kinds of
+  // face of a plane together, so the edge values they share (and the next
+  // plane's, read again one step later) come from cache
   const int k = rblk(blockIdx.x, gridDim.x, d.rev) * RX + threadIdx.x,
             j = rblk(blockIdx.y, gridDim.y, d.rev) * RY + threadIdx.y;
-  const int zt = d.m0 + 2 * d.n0;
-  for (int z = rblk(blockIdx.z, gridDim.z, d.rev); z < zt; z += gridDim.z) {
-    double phi, w;
-    long long q;
-    if (z < d.m0) {  // r-face (i < m0, j < n1, k < n2)
-      const int i = z;
-      if (j >= d.n1 || k >= d.n2) continue;
-      q = ((long long)i * d.n1 + j) * d.n2 + k;
+  int i0, i1;
+  plane_run(d.m0, rblk(blockIdx.z, gridDim.z, d.rev), gridDim.z, i0, i1);
+  double *Pr = Phi, *Pt = Phi + d.nf[0], *Pp = Phi + d.nf[0] + d.nf[1];
+  for (int i = i0; i < i1; ++i) {
+    if (j < d.n1 && k < d.n2) {  // r-face (i < m0, j < n1, k < n2)
       const int kp = nxt(k, d.n2, d.per2), jp = nxt(j, d.n1, d.per1);
       const bool f1 = fixed_t(d, i, k), f2 = fixed_p(d, i, jp), f3 = fixed_t(d, i, kp),
                  f4 = fixed_p(d, i, j);
-      if (KIND == RK_WEIGHT)
-        phi = 1.0;
-      else if (KIND == RK_COUNT)
-        phi = (!f1) + (!f2) + (!f3) + (!f4);
-      else
-        phi = ev<MASK>(E, it(d, i, j, k), f1) + ev<MASK>(E, ip(d, i, jp, k), f2) -
-              ev<MASK>(E, it(d, i, j, kp), f3) - ev<MASK>(E, ip(d, i, j, k), f4);
-      w = tb(d, R_W, i) * tb(d, R_W + 1, j) * tb(d, R_W + 2, k);
-    } else if (z < d.m0 + d.n0) {  // t-face (i < n0, j < m1, k < n2)
-      const int i = z - d.m0;
-      if (j >= d.m1 || k >= d.n2) continue;
-      q = d.nf[0] + ((long long)i * d.m1 + j) * d.n2 + k;
-      const int kp = nxt(k, d.n2, d.per2), iq = nxt(i, d.n0, d.per0);
+      double flux = 0.0;
+      if (KIND == RK_FLUX)
+        flux = ev<MASK>(E, it(d, i, j, k), f1) + ev<MASK>(E, ip(d, i, jp, k), f2) -
+               ev<MASK>(E, it(d, i, j, kp), f3) - ev<MASK>(E, ip(d, i, j, k), f4);
+      const double w = tb(d, R_W, i) * tb(d, R_W + 1, j) * tb(d, R_W + 2, k);
+      Pr[((long long)i * d.n1 + j) * d.n2 + k] = w * face_val<KIND>(f1, f2, f3, f4, flux);
+    }
+    if (i >= d.n0) continue;
+    const int iq = nxt(i, d.n0, d.per0);
+    if (j < d.m1 && k < d.n2) {  // t-face (i < n0, j < m1, k < n2)
+      const int kp = nxt(k, d.n2, d.per2);
       const bool f1 = fixed_r(d, j, kp), f2 = fixed_r(d, j, k), f3 = fixed_p(d, iq, j),
                  f4 = fixed_p(d, i, j);
-      if (KIND == RK_WEIGHT)
-        phi = 1.0;
-      else if (KIND == RK_COUNT)
-        phi = (!f1) + (!f2) + (!f3) + (!f4);
-      else
-        phi = ev<MASK>(E, ir(d, i, j, kp), f1) - ev<MASK>(E, ir(d, i, j, k), f2) -
-              ev<MASK>(E, ip(d, iq, j, k), f3) + ev<MASK>(E, ip(d, i, j, k), f4);
-      w = tb(d, T_W, i) * tb(d, T_W + 1, j) * tb(d, T_W + 2, k);
-    } else {  // p-face (i < n0, j < n1, k < m2)
-      const int i = z - d.m0 - d.n0;
-      if (j >= d.n1 || k >= d.m2) continue;
-      q = d.nf[0] + d.nf[1] + ((long long)i * d.n1 + j) * d.m2 + k;
-      const int iq = nxt(i, d.n0, d.per0), jq = nxt(j, d.n1, d.per1);
+      double flux = 0.0;
+      if (KIND == RK_FLUX)
+        flux = ev<MASK>(E, ir(d, i, j, kp), f1) - ev<MASK>(E, ir(d, i, j, k), f2) -
+               ev<MASK>(E, ip(d, iq, j, k), f3) + ev<MASK>(E, ip(d, i, j, k), f4);
+      const double w = tb(d, T_W, i) * tb(d, T_W + 1, j) * tb(d, T_W + 2, k);
+      Pt[((long long)i * d.m1 + j) * d.n2 + k] = w * face_val<KIND>(f1, f2, f3, f4, flux);
+    }
+    if (j < d.n1 && k < d.m2) {  // p-face (i < n0, j < n1, k < m2)
+      const int jq = nxt(j, d.n1, d.per1);
       const bool f1 = fixed_t(d, iq, k), f2 = fixed_t(d, i, k), f3 = fixed_r(d, jq, k),
                  f4 = fixed_r(d, j, k);
-      if (KIND == RK_WEIGHT)
-        phi = 1.0;
-      else if (KIND == RK_COUNT)
-        phi = (!f1) + (!f2) + (!f3) + (!f4);
-      else
-        phi = ev<MASK>(E, it(d, iq, j, k), f1) - ev<MASK>(E, it(d, i, j, k), f2) -
-              ev<MASK>(E, ir(d, i, jq, k), f3) + ev<MASK>(E, ir(d, i, j, k), f4);
-      w = tb(d, P_W, i) * tb(d, P_W + 1, j) * tb(d, P_W + 2, k);
+      double flux = 0.0;
+      if (KIND == RK_FLUX)
+        flux = ev<MASK>(E, it(d, iq, j, k), f1) - ev<MASK>(E, it(d, i, j, k), f2) -
+               ev<MASK>(E, ir(d, i, jq, k), f3) + ev<MASK>(E, ir(d, i, j, k), f4);
+      const double w = tb(d, P_W, i) * tb(d, P_W + 1, j) * tb(d, P_W + 2, k);
+      Pp[((long long)i * d.n1 + j) * d.m2 + k] = w * face_val<KIND>(f1, f2, f3, f4, flux);
     }
-    Phi[q] = w * phi;
   }
 }
 
@@ -160,94 +165,94 @@ struct RArgs {
 };
 
 template <int MODE>
+__device__ __forceinline__ void consume(const RArgs &a, long long e, bool fixed, double h,
+                                        double s, double wsum, double &acc1) {
+  if (MODE == RC_F) {
+    a.out[e] = fixed ? 0.0 : -a.eta * s / h;
+  } else if (MODE == RC_AY) {
+    const double pv = a.in[e];
+    const double yv = fixed ? 0.0 : h * pv + a.dt * a.eta * s;
+    a.out[e] = yv;
+    acc1 += pv * yv;
+  } else if (MODE == RC_RHS) {
+    const double en = a.in[e];
+    const double bv = fixed ? 0.0 : h * en - a.dt * a.eta * s;
+    a.out[e] = bv;
+    a.out2[e] = fixed ? 0.0 : 1.0 / (h + a.dt * a.eta * wsum);
+    if (fixed) a.xfix[e] = en;
+    acc1 += bv * bv;
+  } else if (MODE == RC_RES) {
+    const double rv = fixed ? 0.0 : a.b[e] - (h * a.in[e] + a.dt * a.eta * s);
+    a.out[e] = rv;
+    acc1 += rv * rv;
+  } else {  // Gershgorin row of eta H^-1 K
+    if (!fixed) acc1 = fmax(acc1, a.eta * wsum / h);
+  }
+}
+
+template <int MODE>
 __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict__ Phi,
                                                const double *__restrict__ Wf, RArgs a) {
   const double *Fr = Phi, *Ft = Phi + d.nf[0], *Fp = Phi + d.nf[0] + d.nf[1];
+  // the values summed for the diagonal: face counts (GERSH) or weights (RHS)
+  const double *X = MODE == RC_GERSH ? Phi : Wf;
+  const double *Xr = X, *Xt = X + d.nf[0], *Xp = X + d.nf[0] + d.nf[1];
+  constexpr bool diag = MODE == RC_GERSH || MODE == RC_RHS;
   double acc1 = 0.0, acc2 = 0.0;
+  // as the face kernel: a contiguous run of r-planes, the three kinds of edge
+  // of a plane together (faces of plane i - 1 were read one step earlier)
   const int k = rblk(blockIdx.x, gridDim.x, d.rev) * RX + threadIdx.x,
             j = rblk(blockIdx.y, gridDim.y, d.rev) * RY + threadIdx.y;
-  const int zt = d.n0 + 2 * d.m0;
-  for (int z = rblk(blockIdx.z, gridDim.z, d.rev); z < zt; z += gridDim.z) {
-    bool fixed;
-    double s = 0.0, h, wsum = 0.0;
-    long long e;
-    // faces of the edge: (flux index, sign) x 4
-    if (z < d.n0) {  // r-edge (i < n0, j < m1, k < m2)
-      const int i = z;
-      if (j >= d.m1 || k >= d.m2) continue;
-      e = ((long long)i * d.m1 + j) * d.m2 + k;
-      fixed = fixed_r(d, j, k);
-      h = tb(d, R_H, i) * tb(d, R_H + 1, j) * tb(d, R_H + 2, k);
+  int i0, i1;
+  plane_run(d.m0, rblk(blockIdx.z, gridDim.z, d.rev), gridDim.z, i0, i1);
+  for (int i = i0; i < i1; ++i) {
+    const int im = prv(i, d.n0, d.per0);
+    // faces of each edge: (flux index, sign) x 4
+    if (i < d.n0 && j < d.m1 && k < d.m2) {  // r-edge (i < n0, j < m1, k < m2)
+      const long long e = ((long long)i * d.m1 + j) * d.m2 + k;
+      const bool fixed = fixed_r(d, j, k);
+      const double h = tb(d, R_H, i) * tb(d, R_H + 1, j) * tb(d, R_H + 2, k);
+      double s = 0.0, wsum = 0.0;
       if (!fixed) {
         const int km = prv(k, d.n2, d.per2), jm = prv(j, d.n1, d.per1);
         const long long t0 = ((long long)i * d.m1 + j) * d.n2;   // Ft(i, j, .)
         const long long p0 = ((long long)i * d.n1 + j) * d.m2;   // Fp(i, j, .)
         const long long p1 = ((long long)i * d.n1 + jm) * d.m2;  // Fp(i, j-1, .)
-        if (MODE == RC_GERSH || MODE == RC_RHS) {
-          const double *X = MODE == RC_GERSH ? Phi : Wf;
-          const double *Xt = X + d.nf[0], *Xp = X + d.nf[0] + d.nf[1];
-          wsum = Xt[t0 + k] + Xt[t0 + km] + Xp[p0 + k] + Xp[p1 + k];
-        }
+        if (diag) wsum = Xt[t0 + k] + Xt[t0 + km] + Xp[p0 + k] + Xp[p1 + k];
         if (MODE != RC_GERSH) s = -Ft[t0 + k] + Ft[t0 + km] + Fp[p0 + k] - Fp[p1 + k];
       }
-    } else if (z < d.n0 + d.m0) {  // t-edge (i < m0, j < n1, k < m2)
-      const int i = z - d.n0;
-      if (j >= d.n1 || k >= d.m2) continue;
-      e = d.ne[0] + ((long long)i * d.n1 + j) * d.m2 + k;
-      fixed = fixed_t(d, i, k);
-      h = tb(d, T_H, i) * tb(d, T_H + 1, j) * tb(d, T_H + 2, k);
+      consume<MODE>(a, e, fixed, h, s, wsum, acc1);
+    }
+    if (j < d.n1 && k < d.m2) {  // t-edge (i < m0, j < n1, k < m2)
+      const long long e = d.ne[0] + ((long long)i * d.n1 + j) * d.m2 + k;
+      const bool fixed = fixed_t(d, i, k);
+      const double h = tb(d, T_H, i) * tb(d, T_H + 1, j) * tb(d, T_H + 2, k);
+      double s = 0.0, wsum = 0.0;
       if (!fixed) {
-        const int km = prv(k, d.n2, d.per2), im = prv(i, d.n0, d.per0);
+        const int km = prv(k, d.n2, d.per2);
         const long long r0 = ((long long)i * d.n1 + j) * d.n2;   // Fr(i, j, .)
         const long long p0 = ((long long)i * d.n1 + j) * d.m2;   // Fp(i, j, .)
         const long long p1 = ((long long)im * d.n1 + j) * d.m2;  // Fp(i-1, j, .)
-        if (MODE == RC_GERSH || MODE == RC_RHS) {
-          const double *X = MODE == RC_GERSH ? Phi : Wf;
-          const double *Xp = X + d.nf[0] + d.nf[1];
-          wsum = X[r0 + k] + X[r0 + km] + Xp[p0 + k] + Xp[p1 + k];
-        }
+        if (diag) wsum = Xr[r0 + k] + Xr[r0 + km] + Xp[p0 + k] + Xp[p1 + k];
         if (MODE != RC_GERSH) s = Fr[r0 + k] - Fr[r0 + km] - Fp[p0 + k] + Fp[p1 + k];
       }
-    } else {  // p-edge (i < m0, j < m1, k < n2)
-      const int i = z - d.n0 - d.m0;
-      if (j >= d.m1 || k >= d.n2) continue;
-      e = d.ne[0] + d.ne[1] + ((long long)i * d.m1 + j) * d.n2 + k;
-      fixed = fixed_p(d, i, j);
-      h = tb(d, P_H, i) * tb(d, P_H + 1, j) * tb(d, P_H + 2, k);
+      consume<MODE>(a, e, fixed, h, s, wsum, acc1);
+    }
+    if (j < d.m1 && k < d.n2) {  // p-edge (i < m0, j < m1, k < n2)
+      const long long e = d.ne[0] + d.ne[1] + ((long long)i * d.m1 + j) * d.n2 + k;
+      const bool fixed = fixed_p(d, i, j);
+      const double h = tb(d, P_H, i) * tb(d, P_H + 1, j) * tb(d, P_H + 2, k);
+      double s = 0.0, wsum = 0.0;
       if (!fixed) {
-        const int jm = prv(j, d.n1, d.per1), im = prv(i, d.n0, d.per0);
+        const int jm = prv(j, d.n1, d.per1);
         const long long r0 = ((long long)i * d.n1 + j) * d.n2;   // Fr(i, j, .)
         const long long r1 = ((long long)i * d.n1 + jm) * d.n2;  // Fr(i, j-1, .)
         const long long t0 = ((long long)i * d.m1 + j) * d.n2;   // Ft(i, j, .)
         const long long t1 = ((long long)im * d.m1 + j) * d.n2;  // Ft(i-1, j, .)
-        if (MODE == RC_GERSH || MODE == RC_RHS) {
-          const double *X = MODE == RC_GERSH ? Phi : Wf;
-          const double *Xt = X + d.nf[0];
-          wsum = X[r0 + k] + X[r1 + k] + Xt[t0 + k] + Xt[t1 + k];
-        }
+        if (diag) wsum = Xr[r0 + k] + Xr[r1 + k] + Xt[t0 + k] + Xt[t1 + k];
         if (MODE != RC_GERSH) s = -Fr[r0 + k] + Fr[r1 + k] + Ft[t0 + k] - Ft[t1 + k];
       }
-    }
-    if (MODE == RC_F) {
-      a.out[e] = fixed ? 0.0 : -a.eta * s / h;
-    } else if (MODE == RC_AY) {
-      const double pv = a.in[e];
-      const double yv = fixed ? 0.0 : h * pv + a.dt * a.eta * s;
-      a.out[e] = yv;
-      acc1 += pv * yv;
-    } else if (MODE == RC_RHS) {
-      const double en = a.in[e];
-      const double bv = fixed ? 0.0 : h * en - a.dt * a.eta * s;
-      a.out[e] = bv;
-      a.out2[e] = fixed ? 0.0 : 1.0 / (h + a.dt * a.eta * wsum);
-      if (fixed) a.xfix[e] = en;
-      acc1 += bv * bv;
-    } else if (MODE == RC_RES) {
-      const double rv = fixed ? 0.0 : a.b[e] - (h * a.in[e] + a.dt * a.eta * s);
-      a.out[e] = rv;
-      acc1 += rv * rv;
-    } else {  // Gershgorin row of eta H^-1 K
-      if (!fixed) acc1 = fmax(acc1, a.eta * wsum / h);
+      consume<MODE>(a, e, fixed, h, s, wsum, acc1);
     }
   }
   const int tid = threadIdx.y * RX + threadIdx.x;
@@ -290,24 +295,25 @@ __global__ void __launch_bounds__(RT)
     p[e] = r[e] * invd[e] + (first ? 0.0 : beta * pold[e]);
 }
 
-// 3D launch: x over phi, y over theta, z strides over the r-planes of the
-// three arrays (about 2048 workgroups)
-dim3 grid3r(const sts_ctx *c, int zt) {
-  const int gx = (c->n2 + 1 + RX - 1) / RX, gy = (c->n1 + 1 + RY - 1) / RY;
-  const int gz = std::max(1, std::min(zt, 2048 / std::max(1, gx * gy)));
-  return dim3(gx, gy, gz);
-}
+// 3D launch: x over phi, y over theta (each sized for the longest of the three
+// arrays along it), z over runs of r-planes.  About 4096 workgroups: enough
+// to keep every CU busy through the tail; more would make the PCG sweeps,
+// each of whose workgroups sums all of the edge sweep's partials, cost more
+// at the smaller grids than the finer split gains.
+constexpr int kResWgs = 4096;
 
-int zt_faces(const sts_ctx *c) {
-  return (c->n0 + (c->bc[0] == STS_BC_PERIODIC ? 0 : 1)) + 2 * c->n0;
-}
-int zt_edges(const sts_ctx *c) {
-  return c->n0 + 2 * (c->n0 + (c->bc[0] == STS_BC_PERIODIC ? 0 : 1));
+dim3 grid3r(const sts_ctx *c) {
+  const int m0 = c->n0 + (c->bc[0] == STS_BC_PERIODIC ? 0 : 1),
+            m1 = c->n1 + (c->bc[2] == STS_BC_PERIODIC ? 0 : 1),
+            m2 = c->n2 + (c->bc[4] == STS_BC_PERIODIC ? 0 : 1);
+  const int gx = (m2 + RX - 1) / RX, gy = (m1 + RY - 1) / RY;
+  const int gz = std::max(1, std::min(m0, kResWgs / std::max(1, gx * gy)));
+  return dim3(gx, gy, gz);
 }
 
 template <int MASK, int KIND>
 void curl_launch(const sts_ctx *c, const RDims &d, const double *E, double *Phi) {
-  hipLaunchKernelGGL((k_rcurl<MASK, KIND>), grid3r(c, zt_faces(c)), dim3(RX, RY), 0, c->stream,
+  hipLaunchKernelGGL((k_rcurl<MASK, KIND>), grid3r(c), dim3(RX, RY), 0, c->stream,
                      d, E, Phi);
 }
 
@@ -315,7 +321,7 @@ void curl_launch(const sts_ctx *c, const RDims &d, const double *E, double *Phi)
 
 // workgroups of the edge sweep (its partial sums), also the 1D grids' size
 int res_parts(const sts_ctx *c) {
-  const dim3 g = grid3r(c, zt_edges(c));
+  const dim3 g = grid3r(c);
   return (int)(g.x * g.y * g.z);
 }
 
@@ -343,7 +349,7 @@ static RDims rdims(const sts_ctx *c) {
 template <int MODE>
 static void curlT_launch(const sts_ctx *c, const RDims &d, const double *Phi, const double *Wf,
                          const RArgs &a) {
-  hipLaunchKernelGGL(k_rcurlT<MODE>, grid3r(c, zt_edges(c)), dim3(RX, RY), 0, c->stream, d, Phi,
+  hipLaunchKernelGGL(k_rcurlT<MODE>, grid3r(c), dim3(RX, RY), 0, c->stream, d, Phi,
                      Wf, a);
 }
 

@@ -1414,7 +1414,7 @@ sts_status apply_F_resistivity(sts_ctx *ctx, const double *E, double *FE) {
   if (!ctx) return STS_EINVAL;
   if (!(ctx->res_eta > 0.0)) FAIL(STS_EINVAL, "resistivity not set (sts_set_resistivity)");
   if (!E || !FE || E == FE) FAIL(STS_EINVAL, "apply_F_resistivity: null or aliased arrays");
-  launch_res_F(ctx, E, ctx->d_rws, FE);
+  launch_res_F(ctx, E, FE);
   LAUNCHCHK();
   return STS_OK;
 }
@@ -1445,9 +1445,11 @@ sts_status resistivity_be_pcg_solve(sts_ctx *ctx, const double *E_n, double *E, 
   if (!(dt > 0.0) || !std::isfinite(dt)) FAIL(STS_EINVAL, "dt must be finite, > 0");
   if (!(rtol >= 0.0) || !std::isfinite(rtol)) FAIL(STS_EINVAL, "bad rtol");
   if (maxit < 0) FAIL(STS_EINVAL, "maxit must be >= 0");
-  const int P = res_parts(ctx);
+  // partial counts: the two-sweep right-hand side and the 1D sweeps (P), the
+  // fused residual and matvec (Pf)
+  const int P = res_parts(ctx), Pf = res_parts_fused(ctx);
   sts_status st;
-  if ((st = ensure_red(ctx, std::max(P, pcg_parts(ctx))))) return st;
+  if ((st = ensure_red(ctx, std::max(std::max(P, Pf), pcg_parts(ctx))))) return st;
   if ((st = dalloc(ctx, (void **)&ctx->d_sc, sizeof(PcgScalars)))) return st;
   const long long ne = ctx->res_ne[0] + ctx->res_ne[1] + ctx->res_ne[2];
   const long long nf = ctx->res_nf[0] + ctx->res_nf[1] + ctx->res_nf[2];
@@ -1458,11 +1460,11 @@ sts_status resistivity_be_pcg_solve(sts_ctx *ctx, const double *E_n, double *E, 
   PcgScalars *sc = ctx->d_sc;
   launch_res_rhs(ctx, E_n, dt, E, b, invd, Phi, Wf, part + 2 * cap);
   LAUNCHCHK();
-  launch_res_residual(ctx, b, E, dt, Phi, r, part + cap);
+  launch_res_residual(ctx, b, E, dt, r, part + cap);
   LAUNCHCHK();
   launch_init_p_n(ctx, ne, r, invd, p0, part, P);
   LAUNCHCHK();
-  launch_finalize_init_n(ctx, part + 2 * cap, P, part + cap, P, part, P, sc, rtol, maxit);
+  launch_finalize_init_n(ctx, part + 2 * cap, P, part + cap, Pf, part, P, sc, rtol, maxit);
   LAUNCHCHK();
   PcgScalars *h = (PcgScalars *)ctx->h_pin;
   double *pold = p0, *pnew = p1;
@@ -1473,8 +1475,8 @@ sts_status resistivity_be_pcg_solve(sts_ctx *ctx, const double *E_n, double *E, 
     // pass B's partials go to regions 2 and 3
     double *part_b = part + 2 * cap;
     const sts_status st = pcg_iterate(ctx, sc, maxit, [&](int it) {
-      launch_res_pass_a(ctx, dt, r, invd, pold, pnew, Phi, y, part, sc, it == 0, part_b, P, it);
-      launch_pass_b_jacobi_n(ctx, ne, E, pnew, r, y, invd, part_b, P, sc, part, P);
+      launch_res_pass_a(ctx, dt, r, invd, pold, pnew, y, part, sc, it == 0, part_b, P, it);
+      launch_pass_b_jacobi_n(ctx, ne, E, pnew, r, y, invd, part_b, P, sc, part, Pf);
       std::swap(pold, pnew);
     });
     if (st) return st;

@@ -186,18 +186,21 @@ void launch_stage_nl(const sts_ctx *c, int mode, const double *ukm1, const doubl
                      double mut_dt, double gt_dt, double kappa0, const double *b0,
                      const double *b1, const double *b2);
 
-// Resistive diffusion on edges (k_resist.hip).  Phi / Wf: face-sized scratch.
-int res_parts(const sts_ctx *c);
-void launch_res_F(const sts_ctx *c, const double *E, double *Phi, double *FE);
+// Resistive diffusion on edges (k_resist.hip).  Phi / Wf: face-sized scratch
+// of the two-sweep form (face sweep, then edge sweep), which the set-up
+// operators use; F, the residual and pass A run one fused sweep.
+int res_parts(const sts_ctx *c);        // two-sweep form's partials; 1D grids
+int res_parts_fused(const sts_ctx *c);  // fused sweep's partials
+void launch_res_F(const sts_ctx *c, const double *E, double *FE);
 void launch_res_gershgorin(const sts_ctx *c, double *Phi, double *part);
 void launch_res_rhs(const sts_ctx *c, const double *En, double dt, double *x, double *b,
                     double *invd, double *Phi, double *Wf, double *part);
 void launch_res_residual(const sts_ctx *c, const double *b, const double *x, double dt,
-                         double *Phi, double *r, double *part);
+                         double *r, double *part);
 // pb != null (and !first): beta and the previous iteration's stopping test
 // from a fused pass B's partials pb (npb), the iteration count being `iters`
 void launch_res_pass_a(const sts_ctx *c, double dt, const double *r, const double *invd,
-                       const double *pold, double *p, double *Phi, double *y, double *part,
+                       const double *pold, double *p, double *y, double *part,
                        const PcgScalars *sc, int first, const double *pb = nullptr,
                        int npb = 0, int iters = 0);
 // PCG pieces over a vector of n entries (k_pcg.hip)

@@ -560,8 +560,11 @@ dim3 grid3r(const sts_ctx *c) {
 // The fused sweep's tiles: strips of kRccRows theta rows, RT / RX strips per
 // workgroup, the phi tiles of the two-sweep form, and runs of r-planes: about
 // kRccWgs workgroups, but runs of at least kRccRun planes (a run's first
-// plane also forms the faces of the plane before it).
-constexpr int kRccRows = 4, kRccWgs = 2048, kRccRun = 8;
+// plane also forms the faces of the plane before it).  Measured at
+// 256x256x512 and 128x128x256: 4-row strips beat 2 and 8 (8 rows need 177
+// VGPRs); runs of 4 planes beat 8 and 16 at the smaller grid and tie at the
+// larger.
+constexpr int kRccRows = 4, kRccWgs = 2048, kRccRun = 4;
 
 void rcc_tiles(const sts_ctx *c, int gx, int &cgy, int &cgz) {
   const int m0 = c->n0 + (c->bc[0] == STS_BC_PERIODIC ? 0 : 1),

@@ -52,6 +52,12 @@ CASES = [
     ("cartesian", (5, 6, 7), (2, 2, 2, 2, 2, 2)),
     ("cartesian", (5, 6, 7), (0, 0, 2, 2, 0, 0)),
     ("cartesian", (4, 3, 5), (2, 2, 0, 0, 2, 2)),
+    # several tiles, theta strips and runs of the fused sweep: phi wrapping
+    # across tiles, theta wrapping across strips, r wrapping at a run's start,
+    # a ragged last phi tile
+    ("spherical", (9, 37, 130), SHELL_BC),
+    ("cartesian", (5, 19, 70), (0, 0, 2, 2, 2, 2)),
+    ("cartesian", (6, 9, 66), (2, 2, 0, 0, 0, 0)),
 ]
 
 
@@ -108,10 +114,15 @@ def test_be_pcg(gpu_lib, coord, n, bc, ratio):
     assert np.array_equal(got[~m], E_n[~m])
 
 
-@pytest.mark.parametrize("k", [1, 5, 12])
-def test_be_pcg_iterates(gpu_lib, k):
+ITER_CASES = [("spherical", (6, 7, 9), SHELL_BC, k) for k in (1, 5, 12)] + \
+    [c + (k,) for c in CASES[7:] for k in (1, 12)]
+
+
+@pytest.mark.parametrize("coord,n,bc,k", ITER_CASES,
+                         ids=[f"{c}-{n}-{b}-{k}" for c, n, b, k in ITER_CASES])
+def test_be_pcg_iterates(gpu_lib, coord, n, bc, k):
     """The k-th PCG iterate equals the oracle's (same recurrence, same PC1)."""
-    g, ctx = _pair(gpu_lib, "spherical", shell_faces(6, 7, 9), SHELL_BC, 0.7)
+    g, ctx = _pair(gpu_lib, coord, _faces(coord, n), bc, 0.7)
     E_n = _smooth_E(g, 5)
     dt = 60.0 * R.gershgorin_dt_euler(g, 0.7)
     ref, res = R.be_pcg(g, E_n, dt, 0.7, rtol=0.0, maxit=k)

@@ -560,7 +560,8 @@ dim3 grid3r(const sts_ctx *c) {
 // The fused sweep's tiles: strips of kRccRows theta rows, RT / RX strips per
 // workgroup, the phi tiles of the two-sweep form, and runs of r-planes: about
 // kRccWgs workgroups, but runs of at least kRccRun planes (a run's first
-// plane also forms the faces of the plane before it).  Measured at
+// plane also forms the faces of the plane before it) unless that leaves
+// fewer than 1024 workgroups.  Measured at
 // 256x256x512 and 128x128x256: 4-row strips beat 2 and 8 (8 rows need 177
 // VGPRs); runs of 4 planes beat 8 and 16 at the smaller grid and tie at the
 // larger.
@@ -572,6 +573,10 @@ void rcc_tiles(const sts_ctx *c, int gx, int &cgy, int &cgz) {
   const int rows = RccGeom<kRccRows>::ROWS;
   cgy = (m1 + rows - 1) / rows;
   cgz = std::max(1, std::min(kRccWgs / std::max(1, gx * cgy), std::max(1, m0 / kRccRun)));
+  // a small grid: runs down to one plane, for parallelism (32x32x64: 47 -> 25
+  // us per BE iteration)
+  if (gx * cgy * cgz < 1024)
+    cgz = std::max(1, std::min(kRccWgs / std::max(1, gx * cgy), m0));
 }
 
 template <int MODE>

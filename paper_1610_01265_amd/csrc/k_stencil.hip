@@ -208,18 +208,7 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
   // own-cell streams (HBM) of plane ip
   auto load_own = [&](int ip, Loads &L) {
     const int c = (ip * g.n1 + jc) * g.n2 + kc;
-    // FP64 conduction pass A streams its coefficients and its outputs
-    // non-temporally (measured: -5% per PCG iteration); the other modes keep
-    // cached coefficient loads
-    constexpr bool pa_nt = OP == OP_SPITZER && MODE == M_PA && sizeof(R) == 8;
-    if (pa_nt) {
-      L.w0 = R(stream_ld(&C.w0[c]));
-      L.w1 = R(stream_ld(&C.w1[c]));
-      L.w2 = R(stream_ld(&C.w2[c]));
-      L.k01 = R(stream_ld(&C.k01[c]));
-      L.k02 = R(stream_ld(&C.k02[c]));
-      L.k12 = R(stream_ld(&C.k12[c]));
-    } else if (OP == OP_SPITZER) {
+    if (OP == OP_SPITZER) {
       L.w0 = R(C.w0[c]);
       L.w1 = R(C.w1[c]);
       L.w2 = R(C.w2[c]);
@@ -244,15 +233,16 @@ __global__ void __launch_bounds__(NT, STS_MARCH_WPE)
     if (MODE == M_RES || MODE == M_RESN) L.x1 = a.b[cc];
   };
   // Same-plane neighbour coefficients of plane ip.  Every one of them is
-  // some thread's own value.  In the stage modes they are passed between
-  // threads: the (k - 1) neighbours by a whole-wave DPP shift (a wavefront
-  // is 64 consecutive k of one row; lane 0 reads the column left of the
-  // tile through the scalar unit), the (j - 1) neighbours through LDS from
-  // the wavefront of the row above (the first row loads them).  This needs
-  // the own values first and a barrier; measured -8 % per RKL2 stage at
-  // 256 x 256 x 512, but +3.5 % per PCG pass A (non-temporal coefficient
-  // streams), which keeps the cached neighbour loads.
-  constexpr bool xlane = OP == OP_SPITZER && MODE != M_PA;
+  // some thread's own value, passed between threads: the (k - 1) neighbours
+  // by a whole-wave DPP shift (a wavefront is 64 consecutive k of one row;
+  // lane 0 reads the column left of the tile through the scalar unit), the
+  // (j - 1) neighbours through LDS from the wavefront of the row above (the
+  // first row loads them).  This needs the own values first and a barrier;
+  // measured at 256 x 256 x 512: -8 % per RKL2 stage and -4.4 % per
+  // Jacobi-PCG iteration (pass A with cached coefficient loads, which beat
+  // non-temporal ones with or without the exchange).  The FP32 form's pass
+  // A measured +1.7 % with it and keeps the loads.
+  constexpr bool xlane = OP == OP_SPITZER && (MODE != M_PA || sizeof(R) == 8);
   auto load_nbr = [&](int ip, Loads &L) {
     if (OP == OP_SPITZER) {
       const int c = (ip * g.n1 + jc) * g.n2 + kc;

@@ -107,3 +107,26 @@ def window_op(w, cell, half, kind="spitzer", nu=1.0):
 
 
 __all__ = ["oracle_spitzer", "window_op", "gpu_spitzer", "small_shell", "relmax", "window_F", "make_workload"]
+
+
+def resistivity_window(R, coord, faces, E, lo, hi, eta):
+    """The oracle's resistive F on the cells [lo, hi) of a grid, taken as a
+    grid of its own with every axis non-periodic.  An edge not on that
+    window's boundary has the same four faces, face weights and edge mass as
+    in the whole grid, so its F there equals the whole grid's.  E: the whole
+    grid's edge values split by component ({'r', 't', 'p'} arrays, whose
+    windows must not wrap).  Returns, per component, (F on the window, mask
+    of its interior edges, the window's index slices into the whole grid's
+    component array)."""
+    (i0, j0, k0), (i1, j1, k1) = lo, hi
+    f0, f1, f2 = faces
+    g = R.edge_grid(coord, f0[i0:i1 + 1], f1[j0:j1 + 1], f2[k0:k1 + 1],
+                    periodic=(False, False, False))
+    sl = {"r": (slice(i0, i1), slice(j0, j1 + 1), slice(k0, k1 + 1)),
+          "t": (slice(i0, i1 + 1), slice(j0, j1), slice(k0, k1 + 1)),
+          "p": (slice(i0, i1 + 1), slice(j0, j1 + 1), slice(k0, k1))}
+    Ew = {c: E[c][sl[c]] for c in "rtp"}
+    for c in "rtp":
+        assert Ew[c].shape == g.shapes[c], (c, Ew[c].shape, g.shapes[c])
+    F = g.split(R.apply_F(g, R.EdgeGrid.join(Ew), eta))
+    return {c: (F[c], ~g.fixed[c], sl[c]) for c in "rtp"}

@@ -5,11 +5,13 @@ F and dt_E to 1e-12 relative, PCG iterates to 1e-12 relative, converged
 solves with iteration counts within one and within the residual bound of
 each other, on small and ragged shells, boxes with every periodicity
 pattern, and the 128 x 128 x 256 shell (12.7M edges, the whole field
-checked)."""
+checked); at 256 x 256 x 512 (101.2M edges, the benchmark's launch), F
+against the oracle on windows of cells and the curl of a gradient on every
+edge."""
 import numpy as np
 import pytest
 
-from helpers import relmax
+from helpers import relmax, resistivity_window
 from oracle import resistivity as R
 from workloads import box_faces, make_workload, shell_faces
 
@@ -188,3 +190,62 @@ def test_shell128_be_pcg(shell128):
     _, b, _, m = R.be_system(g, E_n, dt, 1.0)
     hmin = np.min(R.EdgeGrid.join(g.H)[m])
     assert np.linalg.norm(got[m] - ref[m]) <= 2.0 * rtol * np.linalg.norm(b) / hmin
+
+
+# ----------------------------------------------------------------------------- 256 x 256 x 512
+@pytest.fixture(scope="module")
+def shell256_res(gpu_lib):
+    """The benchmark's resistivity grid: 256 x 256 x 512 cells, 101.2M edges,
+    the fused sweep in the benchmark's launch (tiles, strips and runs)."""
+    faces = shell_faces(256, 256, 512)
+    ctx = gpu_lib.Context(gpu_lib.SPHERICAL, *faces, SHELL_BC)
+    ctx.set_resistivity(1.0)
+    yield faces, ctx
+    ctx.close()
+
+
+def _split_full(sizes, shapes, v):
+    out, o = {}, 0
+    for c, n, sh in zip("rtp", sizes, shapes):
+        out[c] = v[o:o + n].reshape(sh)
+        o += n
+    return out
+
+
+SHAPES256 = [(256, 257, 512), (257, 256, 512), (257, 257, 512)]
+
+
+def test_shell256_F_windows(shell256_res):
+    """F at full size against the oracle on windows of cells, each taken as a
+    grid of its own (its interior edges have the whole grid's F): at the inner
+    r and theta boundaries, across a run, a tile, a theta tile and strip
+    boundary, and at the outer r and theta corner."""
+    faces, ctx = shell256_res
+    sizes = ctx.resistivity_sizes()
+    assert [int(np.prod(s)) for s in SHAPES256] == list(sizes)
+    E = np.random.default_rng(21).standard_normal(sum(sizes))
+    F = _split_full(sizes, SHAPES256, _host(ctx.apply_F_resistivity(_cuda(E))))
+    Es = _split_full(sizes, SHAPES256, E)
+    windows = [((0, 0, 0), (6, 7, 9)), ((14, 12, 58), (22, 21, 70)),
+               ((127, 30, 250), (133, 36, 262)), ((250, 249, 500), (256, 256, 511))]
+    for lo, hi in windows:
+        win = resistivity_window(R, "spherical", faces, Es, lo, hi, 1.0)
+        scale = max(np.max(np.abs(w[0])) for w in win.values())
+        for c, (Fw, m, sl) in win.items():
+            assert m.any()
+            err = np.max(np.abs(F[c][sl][m] - Fw[m]))
+            assert err <= 1e-12 * scale, (lo, hi, c, err / scale)
+
+
+def test_shell256_F_of_gradient_vanishes(shell256_res):
+    """At full size the curl of a discrete gradient is zero on every edge."""
+    faces, ctx = shell256_res
+    sizes = ctx.resistivity_sizes()
+    phi = np.random.default_rng(22).standard_normal((257, 257, 512))
+    E = R.EdgeGrid.join({"r": phi[1:] - phi[:-1], "t": phi[:, 1:] - phi[:, :-1],
+                         "p": np.roll(phi, -1, axis=2) - phi})
+    del phi
+    F = _host(ctx.apply_F_resistivity(_cuda(E)))
+    scale = float(np.max(np.abs(_host(ctx.apply_F_resistivity(
+        _cuda(np.random.default_rng(23).standard_normal(sum(sizes))))))))
+    assert np.max(np.abs(F)) <= 1e-12 * scale

@@ -210,3 +210,21 @@ def test_gershgorin_matches_dense_row_sums():
     assert R.gershgorin_dt_euler(g, 1.3) == pytest.approx(dense, rel=1e-13)
     lam = np.max(np.abs(np.linalg.eigvals(A)))
     assert 2.0 / lam >= dense  # Gershgorin bounds |lambda|_max from above
+
+
+@pytest.mark.parametrize("lo,hi", [((0, 0, 0), (5, 6, 7)), ((2, 3, 4), (7, 9, 12)),
+                                   ((5, 6, 12), (10, 12, 19))])
+def test_window_F_equals_whole_grid(lo, hi):
+    """F on a window of cells, as a non-periodic grid of its own, equals the
+    whole grid's F at the window's interior edges (the check the full-size
+    GPU test makes on sampled windows)."""
+    from helpers import resistivity_window
+    faces = shell_faces(10, 12, 20)
+    g = R.edge_grid("spherical", *faces)
+    E = np.random.default_rng(3).standard_normal(sum(g.sizes))
+    F = g.split(R.apply_F(g, E, 0.8))
+    win = resistivity_window(R, "spherical", faces, g.split(E), lo, hi, 0.8)
+    scale = max(np.max(np.abs(F[c])) for c in "rtp")
+    for c, (Fw, m, sl) in win.items():
+        assert m.any()
+        assert np.max(np.abs(Fw[m] - F[c][sl][m])) <= 1e-14 * scale, c

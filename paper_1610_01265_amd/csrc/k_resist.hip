@@ -345,9 +345,10 @@ __global__ void __launch_bounds__(RT) k_rcurlT(RDims d, const double *__restrict
 //          first (row ja - 1);
 //   i - 1: kept per row from the previous plane (formed at the run's start).
 // E_p and E_t of plane i + 1 at (j, k) are plane i + 1's own values one plane
-// later, and E_r(i, j + 1) is the next row's: each is read once.  Face values
-// and edge sums are the same expressions, in the same order, as the two-sweep
-// form's.
+// later, and E_r(i, j + 1) is the next row's: a strip reads each of its own
+// values once (the halo row and column come on top: 1.6x the algorithmic
+// bytes in all at 256 x 256 x 512).  Face values and edge sums are the same
+// expressions, in the same order, as the two-sweep form's.
 template <int CR>
 struct RccGeom {
   static constexpr int ROWS = CR * (RT / RX);  // theta rows of a workgroup tile
@@ -363,7 +364,8 @@ __device__ __forceinline__ int opaque_s(int v) {
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 

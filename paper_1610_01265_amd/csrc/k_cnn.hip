@@ -127,8 +127,21 @@ __global__ void __launch_bounds__(256)
 
   const int grp = lane >> 4, cl = lane & 15;
   const int j = j0 + wv;
+  // CV_MASK: the mask entries of output plane i (this lane's 4 channels of
+  // its 4 cells; 1 where there is no mask or no cell), loaded before the
+  // plane's MFMAs so that their latency runs under them
+  auto load_mask = [&](int i, uint2 *mv) {
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int k = k0 + 16 * nb + cl;
+      const long long cell = (long long)i * n12 + (long long)j * g.n2 + k;
+      mv[nb] = (mask && j < g.n1 && k < g.n2)
+                   ? *reinterpret_cast<const uint2 *>(mask + cell * CC + 4 * grp)
+                   : make_uint2(0x3F803F80u, 0x3F803F80u);  // bf16 1.0 x 4
+    }
+  };
   // output plane i from input planes i-1, i, i+1 of the ring
-  auto compute = [&](int i) {
+  auto compute = [&](int i, const uint2 *mv) {
     f32x4 acc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -172,11 +185,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int e = 0; e < 4; ++e) o[e] = (__bf16)fmaxf(acc[nb][e] + bias[co0 + e], 0.0f);
           } else {  // CV_MASK
-            __bf16 mk[4] = {(__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f};
-            if (mask) {
-              const uint2 mv = *reinterpret_cast<const uint2 *>(mask + cell * CC + co0);
-              __builtin_memcpy(mk, &mv, 8);
-            }
+            __bf16 mk[4];
+            __builtin_memcpy(mk, &mv[nb], 8);
 #pragma unroll
             for (int e = 0; e < 4; ++e) o[e] = (__bf16)((float)mk[e] > 0.0f ? acc[nb][e] : 0.0f);
           }
@@ -191,12 +201,18 @@ __global__ void __launch_bounds__(256)
   // meanwhile the inputs of the next iteration, i+PP+1 .. i+2PP, are loaded
   // into registers and staged over the planes i-1 .. i+PP-2 afterwards
   for (int i = i0; i < i1; i += PP) {
+    uint2 mv[PP][4];
+    if (MODE == CV_MASK) {
+#pragma unroll
+      for (int q = 0; q < PP; ++q)
+        if (i + q < i1) load_mask(i + q, mv[q]);
+    }
 #pragma unroll
     for (int q = 0; q < PP; ++q)
       if (i + PP + 1 + q <= i1) load_plane(i + PP + 1 + q, v[q]);
 #pragma unroll
     for (int q = 0; q < PP; ++q)
-      if (i + q < i1) compute(i + q);
+      if (i + q < i1) compute(i + q, mv[q]);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PP; ++q)

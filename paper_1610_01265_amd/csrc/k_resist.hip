@@ -16,10 +16,12 @@
 // on interior edges; edges lying in a non-periodic boundary surface hold
 // their values.  Every weight is a product of three 1D tables.
 //
-// Kernels: face fluxes w C E (optionally with only the interior or only the
-// fixed edges of E), and an edge sweep C^T (w Phi) fused with its consumer
-// (F, the BE matvec with the p . y partial, the BE right-hand side with the
-// diagonal, the initial residual).
+// Kernels: one fused sweep for the operators applied every iteration (F, the
+// BE matvec with the p . y partial, the initial residual), whose face values
+// never leave registers; and, for the set-up operators, a face sweep w C E
+// (or the face weights, or the Gershgorin face counts) into memory followed
+// by an edge sweep C^T (w Phi) fused with its consumer (the Gershgorin rows,
+// the BE right-hand side with the diagonal).
 #include "k_common.h"
 #include "k_reduce.h"
 
